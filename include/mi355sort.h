@@ -1,0 +1,146 @@
+/*
+ * mi355sort.h -- C ABI of the MI355X (gfx950) sort library.
+ *
+ * The library computes the result of the paper's "scatter / sort / merge"
+ * method (El-Nashar, IJDPS 2(3) 2011, Section 3.2, Figure 1): a list of n keys
+ * is split into p contiguous parts, every part is sorted, and the sorted parts
+ * are merged into one ordered list.  Every call produces the STABLE ASCENDING
+ * order: keys in the key type's natural order (signed for MS_KEY_I32, unsigned
+ * otherwise), equal keys in their original order, optional 32-bit values
+ * travelling with their keys.  All arithmetic is integer, so results are
+ * exact and deterministic.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers are DEVICE pointers (hipMalloc / torch CUDA tensors) unless the
+ *    comment says (host).  The caller owns every buffer.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls only enqueue work on that stream and return; results are ready
+ *    when the stream is synchronised.  Nothing is allocated inside a call:
+ *    scratch space is the caller's workspace `ws` of `ws_bytes` bytes, whose
+ *    size ms_workspace_size() reports.  The workspace content on entry does
+ *    not matter and is undefined afterwards; two calls in flight at once must
+ *    not share a workspace.
+ *  - Keys are 4 bytes (MS_KEY_I32, MS_KEY_U32) or 8 bytes (MS_KEY_U64), values
+ *    are uint32_t.  Arrays are dense, element i at byte offset i * size.
+ *    Device pointers must be aligned to their element size.
+ *  - Segment / run offsets are a device array of uint64_t with count+1
+ *    entries: off[0] = 0, non-decreasing, off[count] = n_total.  The host
+ *    never reads them; an offsets array that breaks these rules gives an
+ *    unspecified order inside [0, n_total) but no access outside it... as
+ *    long as every off[i] <= n_total.
+ *  - Errors are return codes; nothing throws across the ABI.  On a non-OK
+ *    return nothing was enqueued, and ms_last_error() (per host thread) holds
+ *    a message.  Device-side faults surface at the next synchronisation, as
+ *    HIP reports them.
+ */
+#ifndef MI355SORT_H
+#define MI355SORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ms_status {
+    MS_OK = 0,
+    MS_EINVAL = 1,  /* bad argument: NULL pointer with n > 0, short workspace, ... */
+    MS_ENOMEM = 2,  /* reserved: the library itself never allocates device memory */
+    MS_EDEVICE = 3, /* a HIP call or kernel launch failed */
+    MS_ENOTSUP = 4  /* unknown key type, or a size beyond what the build supports */
+} ms_status;
+
+/* Key types.  Section 3.2 never states the key type; Figure 2's swap
+ * temporary is an int, so signed 32-bit keys are the baseline. */
+typedef enum ms_key_type { MS_KEY_I32 = 0, MS_KEY_U32 = 1, MS_KEY_U64 = 2 } ms_key_type;
+
+typedef enum ms_op {
+    MS_OP_SORT_KEYS = 0,
+    MS_OP_SORT_PAIRS = 1,
+    MS_OP_SORT_SEGMENTED = 2,
+    MS_OP_MERGE_RUNS = 3
+} ms_op;
+
+/*
+ * Workspace bytes a call of `op` needs (written to *bytes, a host pointer).
+ * n_total is the number of keys; num_segments the number of segments or runs
+ * (ignored for the whole-list sorts); has_values selects the key/value form.
+ * The figure depends only on the arguments, never on the data, so a serving
+ * layer can admit work by exact bytes.  Returns MS_EINVAL for a NULL `bytes`,
+ * MS_ENOTSUP for an unknown key type or op.
+ */
+ms_status ms_workspace_size(ms_op op, ms_key_type kt, int has_values, uint64_t n_total,
+                            uint64_t num_segments, size_t *bytes);
+
+/*
+ * Sort n keys (the whole list: Figure 1 with p = 1).  keys_out may equal
+ * keys_in (in-place); otherwise the two must not overlap.  n = 0 is a no-op.
+ * Errors: MS_EINVAL (NULL pointer with n > 0, workspace smaller than
+ * ms_workspace_size(MS_OP_SORT_KEYS, ...)), MS_ENOTSUP (unknown key type).
+ */
+ms_status sort_keys(const void *keys_in, void *keys_out, uint64_t n, ms_key_type kt, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/*
+ * Sort n (key, value) pairs by key, stably: a value moves with its key and
+ * equal keys keep their input order.  In-place is allowed when keys_out ==
+ * keys_in AND vals_out == vals_in.  Errors as for sort_keys.
+ */
+ms_status sort_pairs(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
+                     uint64_t n, ms_key_type kt, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The scatter and sorting phases of Figure 1 for many lists at once: each
+ * segment [seg_offsets[s], seg_offsets[s+1]) of the input is sorted on its
+ * own (no item crosses a segment boundary; empty segments are allowed).
+ * vals_in / vals_out may both be NULL for a key-only sort.  In-place is
+ * allowed under the same rule as sort_pairs.  num_segments = 0 requires
+ * n_total = 0.  Errors: MS_EINVAL for NULL pointers with n_total > 0, a NULL
+ * offsets array with num_segments > 0, num_segments = 0 with n_total > 0, a
+ * short workspace, or only one of vals_in / vals_out given.
+ */
+ms_status sort_segmented(const void *keys_in, const uint32_t *vals_in, void *keys_out,
+                         uint32_t *vals_out, const uint64_t *seg_offsets, uint64_t num_segments,
+                         uint64_t n_total, ms_key_type kt, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The merge phase (Figure 1 merge loop; Section 3.2.2 master merge): num_runs
+ * adjacent runs [run_offsets[r], run_offsets[r+1]), each already sorted
+ * ascending, are combined into one sorted list.  On equal keys the item from
+ * the earlier run comes first, so the result is the stable sort of the
+ * concatenation whichever merge schedule is used.  keys_out must not overlap
+ * keys_in (nor vals_out vals_in).  Runs that are not sorted give an
+ * unspecified order (never an out-of-bounds access).  Errors as for
+ * sort_segmented; num_runs = 0 is MS_EINVAL.
+ */
+ms_status merge_runs(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
+                     const uint64_t *run_offsets, uint64_t num_runs, uint64_t n_total,
+                     ms_key_type kt, void *ws, size_t ws_bytes, void *stream);
+
+/* Text describing the last non-OK status returned on this host thread
+ * ("" if none).  The pointer stays valid until the thread's next call. */
+const char *ms_last_error(void);
+
+/*
+ * Kernel timing (instrumentation for benchmarks).  While enabled, every
+ * kernel the library enqueues is bracketed by HIP events on its own stream;
+ * ms_timing_read() synchronises on those events and returns, per kernel name,
+ * the launch count and the summed duration.  names_out receives up to
+ * max_entries NUL-terminated names of at most 63 characters (host array of
+ * max_entries * 64 chars), count_out and ms_out the matching figures (host
+ * arrays).  Returns the number of distinct kernels seen (which may exceed
+ * max_entries).  ms_timing_enable(0) stops recording; ms_timing_reset()
+ * clears what was recorded.  Not for use while other threads call the
+ * library.
+ */
+ms_status ms_timing_enable(int on);
+ms_status ms_timing_reset(void);
+int ms_timing_read(char *names_out, uint64_t *count_out, double *ms_out, int max_entries);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MI355SORT_H */

@@ -1,0 +1,213 @@
+// merge.hip -- the merge phase: stable merge of adjacent sorted runs (merge_runs).
+//
+// The paper's merge phase combines the sorted parts into one ordered list,
+// either by neighbour exchanges (Figure 1 merge loop) or by the master
+// merging every part (Section 3.2.2).  With the left run's item first on
+// equal keys, every schedule gives the same list: the stable sort of the
+// concatenation.  Here the runs are merged in ceil(log2 R) rounds of pairwise
+// merges, each round one launch over all output positions: round r merges
+// groups of 2^r input runs pairwise, (group 2j, group 2j+1), and copies an
+// unpaired last group.
+//
+// Each thread produces kItems consecutive outputs.  It finds the pair that
+// holds its first output, then the merge-path co-rank of that output's
+// diagonal (how many of the first d outputs come from the left run) by
+// binary search, and merges sequentially from there, crossing into the next
+// pair if its outputs span a pair boundary.  Outputs are staged in LDS and
+// written with coalesced stores.
+#include "ms_device.hpp"
+#include "ms_runtime.hpp"
+
+namespace ms {
+namespace {
+
+template <typename K>
+struct MergeCfg {
+  static constexpr int kThreads = 256;
+  static constexpr int kItems = sizeof(K) == 4 ? 8 : 4;
+  static constexpr int kTile = kThreads * kItems;
+};
+
+__device__ __forceinline__ uint64_t clamp_off(const uint64_t* off, uint64_t idx, uint64_t n) {
+  const uint64_t v = off[idx];
+  return v < n ? v : n;
+}
+
+// Boundary of group g of `width` runs: run_offsets[min(g*width, nruns)],
+// clamped to n and made non-decreasing against the previous boundary.
+__device__ __forceinline__ uint64_t group_begin(const uint64_t* off, uint64_t nruns, uint64_t width, uint64_t g,
+                                                uint64_t n) {
+  const uint64_t idx = g * width < nruns ? g * width : nruns;
+  return clamp_off(off, idx, n);
+}
+
+template <typename K, bool VALS>
+__global__ __launch_bounds__(MergeCfg<K>::kThreads) void merge_round_kernel(
+    const K* __restrict__ src, const uint32_t* __restrict__ srcv, K* __restrict__ dst, uint32_t* __restrict__ dstv,
+    const uint64_t* __restrict__ off, uint64_t nruns, uint64_t n, uint64_t width, K flip) {
+  constexpr int kThreads = MergeCfg<K>::kThreads;
+  constexpr int kItems = MergeCfg<K>::kItems;
+  constexpr int kTile = MergeCfg<K>::kTile;
+  __shared__ K s_out[kTile];
+  __shared__ uint32_t s_outv[VALS ? kTile : 1];
+
+  const int tid = threadIdx.x;
+  const uint64_t tile_begin = static_cast<uint64_t>(blockIdx.x) * kTile;
+  uint64_t p = tile_begin + static_cast<uint64_t>(tid) * kItems;
+  const uint64_t ngroups = (nruns + width - 1) / width;
+  const uint64_t npairs = (ngroups + 1) / 2;
+
+  int produced = 0;
+  while (produced < kItems && p < n) {
+    // Last pair whose start is <= p (pair starts are non-decreasing).
+    uint64_t lo = 0, hi = npairs;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) / 2;
+      if (group_begin(off, nruns, width, 2 * mid, n) <= p)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const uint64_t j = lo;
+    uint64_t a0 = group_begin(off, nruns, width, 2 * j, n);
+    uint64_t a1 = group_begin(off, nruns, width, 2 * j + 1, n);
+    uint64_t b1 = (j + 1 == npairs) ? n : group_begin(off, nruns, width, 2 * j + 2, n);
+    if (a1 < a0) a1 = a0;
+    if (b1 < a1) b1 = a1;
+    if (p < a0 || p >= b1) {  // offsets that break the contract: emit nothing more
+      break;
+    }
+    const uint64_t la = a1 - a0, lb = b1 - a1;
+    const uint64_t d = p - a0;
+    // co-rank: i = number of left-run items among the first d outputs
+    uint64_t ilo = d > lb ? d - lb : 0, ihi = d < la ? d : la;
+    while (ilo < ihi) {
+      const uint64_t mid = (ilo + ihi) / 2;
+      if (flip_key(src[a0 + mid], flip) <= flip_key(src[a1 + (d - 1 - mid)], flip))
+        ilo = mid + 1;
+      else
+        ihi = mid;
+    }
+    uint64_t i = ilo, k = d - ilo;
+    while (produced < kItems && p < b1) {
+      bool take_a;
+      if (i >= la)
+        take_a = false;
+      else if (k >= lb)
+        take_a = true;
+      else
+        take_a = flip_key(src[a0 + i], flip) <= flip_key(src[a1 + k], flip);
+      const uint64_t from = take_a ? a0 + i : a1 + k;
+      s_out[tid * kItems + produced] = src[from];
+      if constexpr (VALS) s_outv[tid * kItems + produced] = srcv[from];
+      if (take_a)
+        ++i;
+      else
+        ++k;
+      ++produced;
+      ++p;
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < kTile; t += kThreads) {
+    const uint64_t q = tile_begin + t;
+    if (q < n) {
+      dst[q] = s_out[t];
+      if constexpr (VALS) dstv[q] = s_outv[t];
+    }
+  }
+}
+
+template <typename K, bool VALS>
+__global__ __launch_bounds__(256) void copy_kernel(const K* __restrict__ src, const uint32_t* __restrict__ srcv,
+                                                   K* __restrict__ dst, uint32_t* __restrict__ dstv, uint64_t n) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    dst[i] = src[i];
+    if constexpr (VALS) dstv[i] = srcv[i];
+  }
+}
+
+struct MergeLayout {
+  size_t alt_k = 0, alt_v = 0, total = 0;
+  int rounds = 0;
+};
+
+int ceil_log2(uint64_t x) {
+  int r = 0;
+  while ((1ull << r) < x) ++r;
+  return r;
+}
+
+MergeLayout merge_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nruns) {
+  MergeLayout L;
+  L.rounds = nruns > 1 ? ceil_log2(nruns) : 0;
+  if (L.rounds < 2) return L;  // one round reads the input and writes the output directly
+  size_t off = 0;
+  L.alt_k = off;
+  off += align_up(n * key_bytes(kt));
+  if (has_vals) {
+    L.alt_v = off;
+    off += align_up(n * sizeof(uint32_t));
+  }
+  L.total = off;
+  return L;
+}
+
+template <typename K, bool VALS>
+ms_status run_merge(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
+                    uint64_t nruns, uint64_t n, K flip, char* ws, const MergeLayout& L, hipStream_t s) {
+  if (L.rounds == 0) {
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    MS_LAUNCH("merge_copy", (copy_kernel<K, VALS>), static_cast<uint32_t>(blocks), 256, s,
+              static_cast<const K*>(kin), vin, static_cast<K*>(kout), vout, n);
+    return MS_OK;
+  }
+  K* alt_k = L.rounds >= 2 ? reinterpret_cast<K*>(ws + L.alt_k) : nullptr;
+  uint32_t* alt_v = (VALS && L.rounds >= 2) ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr;
+  const K* src = static_cast<const K*>(kin);
+  const uint32_t* srcv = vin;
+  const uint64_t blocks = (n + MergeCfg<K>::kTile - 1) / MergeCfg<K>::kTile;
+  if (blocks > 0x7fffffffull) return fail(MS_ENOTSUP, "merge_runs: list too long");
+  for (int r = 0; r < L.rounds; ++r) {
+    const bool to_out = ((L.rounds - 1 - r) % 2) == 0;
+    K* dst = to_out ? static_cast<K*>(kout) : alt_k;
+    uint32_t* dstv = to_out ? vout : alt_v;
+    MS_LAUNCH("merge_round", (merge_round_kernel<K, VALS>), static_cast<uint32_t>(blocks), MergeCfg<K>::kThreads, s,
+              src, srcv, dst, dstv, off, nruns, n, 1ull << r, flip);
+    src = dst;
+    srcv = dstv;
+  }
+  return MS_OK;
+}
+
+}  // namespace
+
+size_t merge_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nruns) {
+  return merge_layout(kt, has_vals, n, nruns).total;
+}
+
+ms_status merge_sorted_runs(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
+                            const uint64_t* offsets, uint64_t nruns, uint64_t n, ms_key_type kt, void* ws,
+                            size_t ws_bytes, hipStream_t s) {
+  const bool vals = vals_in != nullptr;
+  const MergeLayout L = merge_layout(kt, vals, n, nruns);
+  if (ws_bytes < L.total || (L.total && !ws))
+    return fail(MS_EINVAL, "merge_runs: workspace too small: %zu bytes given, %zu needed", ws_bytes, L.total);
+  char* w = static_cast<char*>(ws);
+  switch (kt) {
+    case MS_KEY_I32:
+      return vals ? run_merge<uint32_t, true>(keys_in, vals_in, keys_out, vals_out, offsets, nruns, n, 0x80000000u, w, L, s)
+                  : run_merge<uint32_t, false>(keys_in, vals_in, keys_out, vals_out, offsets, nruns, n, 0x80000000u, w, L, s);
+    case MS_KEY_U32:
+      return vals ? run_merge<uint32_t, true>(keys_in, vals_in, keys_out, vals_out, offsets, nruns, n, 0u, w, L, s)
+                  : run_merge<uint32_t, false>(keys_in, vals_in, keys_out, vals_out, offsets, nruns, n, 0u, w, L, s);
+    case MS_KEY_U64:
+      return vals ? run_merge<uint64_t, true>(keys_in, vals_in, keys_out, vals_out, offsets, nruns, n, 0ull, w, L, s)
+                  : run_merge<uint64_t, false>(keys_in, vals_in, keys_out, vals_out, offsets, nruns, n, 0ull, w, L, s);
+  }
+  return fail(MS_ENOTSUP, "merge_runs: unknown key type %d", static_cast<int>(kt));
+}
+
+}  // namespace ms

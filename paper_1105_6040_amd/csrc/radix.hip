@@ -1,0 +1,490 @@
+// radix.hip -- stable LSD radix sort of one list on gfx950 (sort_keys, sort_pairs).
+//
+// This is the "sort phase" of the paper's scatter / sort / merge method
+// (Section 3.2, Figure 1 step 9) for a whole list, redesigned for one GPU:
+// instead of a comparison sort per process, the list is sorted by 8-bit
+// digits from least to most significant, each digit pass a stable counting
+// scatter, so the order of equal keys is kept (the paper's bubble sort keeps
+// it too; its merge sort does with a left-first merge).
+//
+// Launch sequence on the caller's stream (no host synchronisation):
+//   1. clear     zero the counters, histograms and first look-back buffer
+//   2. histogram one read of all keys -> one 256-bin histogram per digit
+//                pass; the last workgroup turns them into digit bases, marks
+//                passes whose digit is the same for every key as trivial, and
+//                writes the ping-pong plan (which buffer each pass reads and
+//                writes) to device memory
+//   3. P passes  onesweep: each workgroup takes the next tile id from an
+//                atomic counter, ranks its tile by digit (wave ballots + LDS
+//                counters), publishes its digit counts, looks back across
+//                earlier tiles for their running prefix (decoupled look-back),
+//                reorders the tile in LDS and writes digit runs coalesced
+//   4. copy      only when the plan needs it (in-place sort with an odd
+//                number of executed passes, or no pass executed)
+// Lists of at most one LDS tile skip all that: one workgroup sorts them in
+// LDS with every pass done on-chip.
+#include "ms_device.hpp"
+#include "ms_lds_sort.hpp"
+#include "ms_runtime.hpp"
+
+namespace ms {
+namespace {
+
+constexpr int kMaxPasses = 8;
+
+struct PassPlan {
+  const void* src_k;
+  void* dst_k;
+  const uint32_t* src_v;
+  uint32_t* dst_v;
+  uint32_t active;  // 0: the digit is constant over the list; pass skipped
+  uint32_t first;   // the first executed pass: apply the key codec on load
+  uint32_t last;    // the final executed pass: undo the key codec on store
+  uint32_t pad;
+};
+
+struct SortPlan {
+  PassPlan pass[kMaxPasses];
+  const void* copy_src_k;
+  void* copy_dst_k;
+  const uint32_t* copy_src_v;
+  uint32_t* copy_dst_v;
+  uint32_t copy;  // 1: copy the n results from copy_src to copy_dst at the end
+  uint32_t num_active;
+  uint32_t pad[2];
+};
+
+struct Buffers {
+  const void* keys_in;
+  void* keys_out;
+  void* alt_k;
+  const uint32_t* vals_in;
+  uint32_t* vals_out;
+  uint32_t* alt_v;
+};
+
+// Onesweep tile geometry: 256 threads (4 waves), each wave ranks 64 x kKpt
+// keys held in registers.  Thread t owns digit t in the look-back and scans.
+template <typename K>
+struct PassCfg {
+  static constexpr int kThreads = 256;
+  static constexpr int kKpt = sizeof(K) == 4 ? 16 : 8;
+  static constexpr int kTile = kThreads * kKpt;
+};
+
+template <typename C>
+__device__ __forceinline__ void atomic_add_c(C* p, C v) {
+  if constexpr (sizeof(C) == 4) {
+    atomicAdd(reinterpret_cast<unsigned int*>(p), static_cast<unsigned int>(v));
+  } else {
+    atomicAdd(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(v));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1. clear: zero two byte ranges (each a multiple of 16 bytes).
+__global__ __launch_bounds__(256) void clear_kernel(uint4* a, size_t a16, uint4* b, size_t b16) {
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  const uint4 z = make_uint4(0, 0, 0, 0);
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a16 + b16; i += stride) {
+    if (i < a16)
+      a[i] = z;
+    else
+      b[i - a16] = z;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2. histogram + plan.
+template <typename K, typename C>
+__global__ __launch_bounds__(256) void histogram_kernel(const K* __restrict__ keys, C n, K flip,
+                                                        C* __restrict__ ghist, C* __restrict__ gbase,
+                                                        uint32_t* done, SortPlan* plan, Buffers buf,
+                                                        int has_vals) {
+  constexpr int P = sizeof(K);        // 8-bit digits
+  constexpr int kCopies = 32 / P;     // counter copies spread same-digit lanes: 32 KB of LDS
+  constexpr int kVec = 16 / sizeof(K);
+  __shared__ uint32_t h[P * kRadix * kCopies];
+  __shared__ C s_scan[kRadix / kWave];
+  __shared__ uint32_t s_active[P];
+  __shared__ uint32_t s_last;
+  const int tid = threadIdx.x;
+
+  for (int i = tid; i < P * kRadix * kCopies; i += 256) h[i] = 0;
+  __syncthreads();
+
+  const uint32_t copy = lane_id() % kCopies;
+  auto count = [&](K k) {
+    k = flip_key(k, flip);
+#pragma unroll
+    for (int p = 0; p < P; ++p) atomicAdd(&h[(p * kRadix + digit_of(k, 8 * p)) * kCopies + copy], 1u);
+  };
+  auto count_vec = [&](const uint4& v) {
+    if constexpr (sizeof(K) == 4) {
+      count(v.x);
+      count(v.y);
+      count(v.z);
+      count(v.w);
+    } else {
+      count((static_cast<uint64_t>(v.y) << 32) | v.x);
+      count((static_cast<uint64_t>(v.w) << 32) | v.z);
+    }
+  };
+
+  // Unaligned head and the tail go through scalar loads in block 0.
+  const uint64_t mis = (reinterpret_cast<uintptr_t>(keys) / sizeof(K)) % kVec;
+  C head = mis ? static_cast<C>(kVec - mis) : C(0);
+  if (head > n) head = n;
+  const C nvec = (n - head) / kVec;
+  const uint4* vbase = reinterpret_cast<const uint4*>(keys + head);
+  const C stride = static_cast<C>(gridDim.x) * 256;
+  C i = static_cast<C>(blockIdx.x) * 256 + tid;
+  for (; i + 3 * stride < nvec; i += 4 * stride) {
+    const uint4 v0 = vbase[i], v1 = vbase[i + stride], v2 = vbase[i + 2 * stride], v3 = vbase[i + 3 * stride];
+    count_vec(v0);
+    count_vec(v1);
+    count_vec(v2);
+    count_vec(v3);
+  }
+  for (; i < nvec; i += stride) count_vec(vbase[i]);
+  if (blockIdx.x == 0) {
+    for (C j = tid; j < head; j += 256) count(keys[j]);
+    for (C j = head + nvec * kVec + tid; j < n; j += 256) count(keys[j]);
+  }
+  __syncthreads();
+
+  for (int b = tid; b < P * kRadix; b += 256) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int c = 0; c < kCopies; ++c) s += h[b * kCopies + c];
+    if (s) atomic_add_c(&ghist[b], static_cast<C>(s));
+  }
+
+  // The last block to finish builds the plan.
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+
+  for (int p = 0; p < P; ++p) {
+    const C c = __hip_atomic_load(&ghist[p * kRadix + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    C total;
+    const C ex = block_exclusive_scan_radix<256>(c, s_scan, &total);
+    gbase[p * kRadix + tid] = ex;
+    const int trivial = __syncthreads_or(c == n);
+    if (tid == 0) s_active[p] = !trivial;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+
+  uint32_t m = 0;
+  for (int p = 0; p < P; ++p) m += s_active[p];
+  const bool inplace = buf.keys_in == buf.keys_out;
+  const void* cur_k = buf.keys_in;
+  const uint32_t* cur_v = buf.vals_in;
+  uint32_t e = 0;
+  for (int p = 0; p < kMaxPasses; ++p) {
+    PassPlan pp = {};
+    if (p < P && s_active[p]) {
+      // The last executed pass must land in keys_out; earlier ones alternate.
+      // In place, the first pass cannot write keys_out (it is being read).
+      const bool to_out = inplace ? (e % 2 == 1) : ((m - 1 - e) % 2 == 0);
+      pp.src_k = cur_k;
+      pp.dst_k = to_out ? buf.keys_out : buf.alt_k;
+      pp.src_v = cur_v;
+      pp.dst_v = has_vals ? (to_out ? buf.vals_out : buf.alt_v) : nullptr;
+      pp.active = 1;
+      pp.first = e == 0;
+      pp.last = e == m - 1;
+      cur_k = pp.dst_k;
+      cur_v = pp.dst_v;
+      ++e;
+    }
+    plan->pass[p] = pp;
+  }
+  plan->copy = 0;
+  plan->copy_src_k = nullptr;
+  plan->copy_dst_k = nullptr;
+  plan->copy_src_v = nullptr;
+  plan->copy_dst_v = nullptr;
+  if (m == 0 && !inplace) {  // every digit constant: the output is the input
+    plan->copy = 1;
+    plan->copy_src_k = buf.keys_in;
+    plan->copy_dst_k = buf.keys_out;
+    plan->copy_src_v = buf.vals_in;
+    plan->copy_dst_v = buf.vals_out;
+  } else if (m > 0 && inplace && (m % 2 == 1)) {  // result ended in the workspace
+    plan->copy = 1;
+    plan->copy_src_k = buf.alt_k;
+    plan->copy_dst_k = buf.keys_out;
+    plan->copy_src_v = buf.alt_v;
+    plan->copy_dst_v = buf.vals_out;
+  }
+  plan->num_active = m;
+}
+
+// ---------------------------------------------------------------------------
+// 3. one onesweep digit pass.
+template <typename K, bool VALS, typename C, typename S>
+__global__ __launch_bounds__(PassCfg<K>::kThreads) void onesweep_kernel(
+    const SortPlan* __restrict__ plan, int pass, C n, K flip, const C* __restrict__ gbase,
+    uint32_t* tile_counter, S* status_cur, S* status_next) {
+  constexpr int kThreads = PassCfg<K>::kThreads;
+  constexpr int kKpt = PassCfg<K>::kKpt;
+  constexpr int kTile = PassCfg<K>::kTile;
+  constexpr int kWaves = kThreads / kWave;
+  using St = Status<S>;
+
+  __shared__ uint32_t s_whist[kWaves][kRadix];  // wave digit counts, then each wave's first slot
+  __shared__ C s_doff[kRadix];                  // output index of the tile's first key of each digit, minus its tile position
+  __shared__ K s_keys[kTile];
+  __shared__ uint32_t s_vals[VALS ? kTile : 1];
+  __shared__ uint32_t s_scan[kRadix / kWave];
+  __shared__ uint32_t s_tile;
+
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const uint32_t lane = lane_id();
+  const PassPlan& pp = plan->pass[pass];
+
+  if (!pp.active) {
+    // Skipped pass: still clear the next pass's look-back row.
+    if (status_next)
+      for (int d = tid; d < kRadix; d += kThreads) status_next[static_cast<size_t>(blockIdx.x) * kRadix + d] = 0;
+    return;
+  }
+
+  if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+  for (int i = tid; i < kWaves * kRadix; i += kThreads) (&s_whist[0][0])[i] = 0;
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  if (status_next)
+    for (int d = tid; d < kRadix; d += kThreads) status_next[static_cast<size_t>(tile) * kRadix + d] = 0;
+
+  const int shift = 8 * pass;
+  const C tile_base = static_cast<C>(tile) * kTile;
+  const K* __restrict__ src = static_cast<const K*>(pp.src_k);
+  const C first = tile_base + static_cast<C>(wave * kWave * kKpt) + lane;
+
+  // Load: wave w holds tile keys [w*64*kKpt, (w+1)*64*kKpt), slot j lane l
+  // is tile key w*64*kKpt + j*64 + l.  Past the end: all-ones keys, which
+  // have the largest digit in every pass and sit after every real key.
+  // Intermediate buffers hold encoded keys; only the input needs the codec.
+  const K in_flip = pp.first ? flip : K(0);
+  K keys[kKpt];
+  uint32_t vals[VALS ? kKpt : 1];
+#pragma unroll
+  for (int j = 0; j < kKpt; ++j) {
+    const C idx = first + static_cast<C>(j * kWave);
+    keys[j] = idx < n ? flip_key(src[idx], in_flip) : ~K(0);
+  }
+  if constexpr (VALS) {
+#pragma unroll
+    for (int j = 0; j < kKpt; ++j) {
+      const C idx = first + static_cast<C>(j * kWave);
+      vals[j] = idx < n ? pp.src_v[idx] : 0u;
+    }
+  }
+
+  // Rank within the wave: peers by ballot, running counts in LDS.  Slots are
+  // processed in index order, lanes within a slot by lane, so equal digits
+  // get increasing ranks in input order (stability).
+  uint32_t rank[kKpt];
+  uint32_t* wh = s_whist[wave];
+  wave_rank(keys, shift, rank, wh);
+  __syncthreads();
+
+  // Per digit: tile count and the tile position of each wave's first key.
+  uint32_t cnt;
+  const uint32_t start = tile_digit_starts<kThreads>(s_whist, s_scan, &cnt);
+
+  if (tid < kRadix) {
+    // Decoupled look-back for digit `tid`.
+    S* st = status_cur + static_cast<size_t>(tile) * kRadix + tid;
+    C excl = 0;
+    if (tile == 0) {
+      status_store(st, St::kInc | static_cast<S>(cnt));
+    } else {
+      status_store(st, St::kAgg | static_cast<S>(cnt));
+      const S* q = st - kRadix;
+      while (true) {
+        const S w = status_load(q);
+        const S flag = w & St::kFlagMask;
+        if (flag == 0) {
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += static_cast<C>(w & St::kValMask);
+        if (flag == St::kInc) break;
+        q -= kRadix;
+      }
+      status_store(st, St::kInc | static_cast<S>(excl + cnt));
+    }
+    s_doff[tid] = gbase[tid] + excl - static_cast<C>(start);
+  }
+  __syncthreads();
+
+  // Reorder the tile by digit in LDS.
+#pragma unroll
+  for (int j = 0; j < kKpt; ++j) {
+    const uint32_t pos = wh[digit_of(keys[j], shift)] + rank[j];
+    s_keys[pos] = keys[j];
+    if constexpr (VALS) s_vals[pos] = vals[j];
+  }
+  __syncthreads();
+
+  // Write digit runs: consecutive threads write consecutive addresses.
+  const C remaining = n - tile_base;
+  const int valid = remaining < static_cast<C>(kTile) ? static_cast<int>(remaining) : kTile;
+  K* __restrict__ dst = static_cast<K*>(pp.dst_k);
+  const K out_flip = pp.last ? flip : K(0);
+#pragma unroll 4
+  for (int i = tid; i < valid; i += kThreads) {
+    const K k = s_keys[i];
+    const C o = s_doff[digit_of(k, shift)] + static_cast<C>(i);
+    dst[o] = k ^ out_flip;
+    if constexpr (VALS) pp.dst_v[o] = s_vals[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 4. copy n results when the plan asks for it.
+template <typename K, bool VALS>
+__global__ __launch_bounds__(256) void plan_copy_kernel(const SortPlan* __restrict__ plan, uint64_t n) {
+  if (!plan->copy) return;
+  const K* __restrict__ sk = static_cast<const K*>(plan->copy_src_k);
+  K* __restrict__ dk = static_cast<K*>(plan->copy_dst_k);
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    dk[i] = sk[i];
+    if constexpr (VALS) plan->copy_dst_v[i] = plan->copy_src_v[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+struct Layout {
+  size_t plan = 0, ctrs = 0, ghist = 0, gbase = 0, status0 = 0, status1 = 0, alt_k = 0, alt_v = 0, total = 0;
+  size_t status_bytes = 0;
+  uint32_t num_tiles = 0;
+  bool big = false;
+  bool small = false;
+};
+
+Layout make_layout(ms_key_type kt, bool has_vals, uint64_t n) {
+  Layout L;
+  const int kb = key_bytes(kt);
+  const int lds_tile = kb == 4 ? LdsCfg<uint32_t>::kTile : LdsCfg<uint64_t>::kTile;
+  if (n <= static_cast<uint64_t>(lds_tile)) {
+    L.small = true;
+    return L;  // no workspace
+  }
+  const int tile = kb == 4 ? PassCfg<uint32_t>::kTile : PassCfg<uint64_t>::kTile;
+  const int P = kb;
+  L.big = n >= (1ull << 30);
+  const size_t cb = L.big ? 8 : 4;  // counter and status word bytes
+  L.num_tiles = static_cast<uint32_t>((n + tile - 1) / tile);
+  size_t off = 0;
+  L.plan = off;
+  off += align_up(sizeof(SortPlan));
+  L.ctrs = off;
+  off += align_up((1 + kMaxPasses) * sizeof(uint32_t));
+  L.ghist = off;
+  off += align_up(P * kRadix * cb);
+  L.gbase = off;
+  off += align_up(P * kRadix * cb);
+  L.status_bytes = align_up(static_cast<size_t>(L.num_tiles) * kRadix * cb);
+  L.status0 = off;
+  off += L.status_bytes;
+  L.status1 = off;
+  off += L.status_bytes;
+  L.alt_k = off;
+  off += align_up(n * kb);
+  if (has_vals) {
+    L.alt_v = off;
+    off += align_up(n * sizeof(uint32_t));
+  }
+  L.total = off;
+  return L;
+}
+
+template <typename K, bool VALS>
+ms_status run_small(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, uint64_t n, K flip,
+                    hipStream_t s) {
+  MS_LAUNCH("lds_sort", (lds_sort_kernel<K, VALS>), 1, LdsCfg<K>::kThreads, s, static_cast<const K*>(kin), vin,
+            static_cast<K*>(kout), vout, static_cast<const uint64_t*>(nullptr),
+            static_cast<const uint32_t*>(nullptr), n, flip);
+  return MS_OK;
+}
+
+template <typename K, bool VALS, typename C, typename S>
+ms_status run_onesweep(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, uint64_t n, K flip,
+                       char* ws, const Layout& L, hipStream_t s) {
+  constexpr int P = sizeof(K);
+  SortPlan* plan = reinterpret_cast<SortPlan*>(ws + L.plan);
+  uint32_t* ctrs = reinterpret_cast<uint32_t*>(ws + L.ctrs);
+  C* ghist = reinterpret_cast<C*>(ws + L.ghist);
+  C* gbase = reinterpret_cast<C*>(ws + L.gbase);
+  S* status[2] = {reinterpret_cast<S*>(ws + L.status0), reinterpret_cast<S*>(ws + L.status1)};
+
+  const size_t a16 = (L.gbase - L.ctrs) / 16;  // counters + histograms
+  const size_t b16 = L.status_bytes / 16;
+  MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), a16,
+            reinterpret_cast<uint4*>(ws + L.status0), b16);
+
+  Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
+  const uint64_t per_block = 256ull * 16;
+  uint64_t hblocks = (n + per_block - 1) / per_block;
+  if (hblocks > 1024) hblocks = 1024;
+  MS_LAUNCH("histogram", (histogram_kernel<K, C>), static_cast<uint32_t>(hblocks), 256, s,
+            static_cast<const K*>(kin), static_cast<C>(n), flip, ghist, gbase, ctrs, plan, buf, VALS ? 1 : 0);
+
+  for (int p = 0; p < P; ++p) {
+    S* next = p + 1 < P ? status[(p + 1) & 1] : nullptr;
+    MS_LAUNCH("onesweep_pass", (onesweep_kernel<K, VALS, C, S>), L.num_tiles, PassCfg<K>::kThreads, s,
+              static_cast<const SortPlan*>(plan), p, static_cast<C>(n), flip,
+              static_cast<const C*>(gbase + p * kRadix), ctrs + 1 + p, status[p & 1], next);
+  }
+  MS_LAUNCH("plan_copy", (plan_copy_kernel<K, VALS>), 1024, 256, s, static_cast<const SortPlan*>(plan), n);
+  return MS_OK;
+}
+
+template <typename K, bool VALS>
+ms_status dispatch(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, uint64_t n, K flip,
+                   void* ws, const Layout& L, hipStream_t s) {
+  if (L.small) return run_small<K, VALS>(kin, vin, kout, vout, n, flip, s);
+  char* w = static_cast<char*>(ws);
+  if (L.big) return run_onesweep<K, VALS, uint64_t, uint64_t>(kin, vin, kout, vout, n, flip, w, L, s);
+  return run_onesweep<K, VALS, uint32_t, uint32_t>(kin, vin, kout, vout, n, flip, w, L, s);
+}
+
+}  // namespace
+
+size_t radix_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n) {
+  return make_layout(kt, has_vals, n).total;
+}
+
+ms_status radix_sort(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
+                     uint64_t n, ms_key_type kt, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (n == 0) return MS_OK;
+  const Layout L = make_layout(kt, vals_in != nullptr, n);
+  if (ws_bytes < L.total || (L.total && !ws))
+    return fail(MS_EINVAL, "workspace too small: %zu bytes given, %zu needed", ws_bytes, L.total);
+  const bool vals = vals_in != nullptr;
+  switch (kt) {
+    case MS_KEY_I32:
+      return vals ? dispatch<uint32_t, true>(keys_in, vals_in, keys_out, vals_out, n, 0x80000000u, ws, L, s)
+                  : dispatch<uint32_t, false>(keys_in, vals_in, keys_out, vals_out, n, 0x80000000u, ws, L, s);
+    case MS_KEY_U32:
+      return vals ? dispatch<uint32_t, true>(keys_in, vals_in, keys_out, vals_out, n, 0u, ws, L, s)
+                  : dispatch<uint32_t, false>(keys_in, vals_in, keys_out, vals_out, n, 0u, ws, L, s);
+    case MS_KEY_U64:
+      return vals ? dispatch<uint64_t, true>(keys_in, vals_in, keys_out, vals_out, n, 0ull, ws, L, s)
+                  : dispatch<uint64_t, false>(keys_in, vals_in, keys_out, vals_out, n, 0ull, ws, L, s);
+  }
+  return fail(MS_ENOTSUP, "unknown key type %d", static_cast<int>(kt));
+}
+
+}  // namespace ms

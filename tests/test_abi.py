@@ -1,0 +1,76 @@
+"""The C-ABI library loads, exports what the header declares, and rejects bad
+arguments on the host before touching a GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1105_6040_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mi355sort.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for fn in ("sort_keys", "sort_pairs", "sort_segmented", "merge_runs", "ms_workspace_size", "ms_last_error"):
+        assert fn in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = N.lib()
+    for fn in declared_functions():
+        assert hasattr(lib, fn), f"{fn} declared in mi355sort.h but not exported"
+
+
+def test_workspace_sizes():
+    ws = N.workspace_size
+    assert ws(N.MS_OP_SORT_KEYS, N.MS_KEY_I32, False, 0) == 0
+    assert ws(N.MS_OP_SORT_KEYS, N.MS_KEY_I32, False, 100) == 0          # one LDS tile: no workspace
+    big = ws(N.MS_OP_SORT_KEYS, N.MS_KEY_I32, False, 2**28)
+    assert 2**28 * 4 <= big <= 2**28 * 5                                  # ping-pong buffer + look-back state
+    pairs = ws(N.MS_OP_SORT_PAIRS, N.MS_KEY_U64, True, 2**26)
+    assert 2**26 * 12 <= pairs
+    assert ws(N.MS_OP_MERGE_RUNS, N.MS_KEY_I32, False, 1000, 2) == 0     # one round: no workspace
+    assert ws(N.MS_OP_MERGE_RUNS, N.MS_KEY_I32, True, 1000, 4) >= 1000 * 8
+    assert ws(N.MS_OP_SORT_SEGMENTED, N.MS_KEY_U32, True, 5000, 7) >= 5000 * 8
+
+
+def test_workspace_size_errors():
+    lib = N.lib()
+    assert lib.ms_workspace_size(0, 0, 0, 10, 0, None) == N.MS_EINVAL
+    out = ctypes.c_size_t()
+    assert lib.ms_workspace_size(0, 7, 0, 10, 0, ctypes.byref(out)) == N.MS_ENOTSUP
+    assert lib.ms_workspace_size(9, 0, 0, 10, 0, ctypes.byref(out)) == N.MS_ENOTSUP
+
+
+def test_host_side_argument_errors():
+    lib = N.lib()
+    # n = 0 is a no-op with any pointers
+    assert lib.sort_keys(None, None, 0, N.MS_KEY_I32, None, 0, None) == N.MS_OK
+    assert lib.sort_keys(None, None, 10, N.MS_KEY_I32, None, 0, None) == N.MS_EINVAL
+    assert "NULL" in N.last_error()
+    assert lib.sort_keys(None, None, 10, 5, None, 0, None) == N.MS_ENOTSUP
+    # short workspace: detected before any launch (pointers are never dereferenced)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.sort_keys(fake, fake, 10**6, N.MS_KEY_I32, None, 0, None) == N.MS_EINVAL
+    assert "workspace" in N.last_error()
+    # pairs: keys in place but values not
+    assert lib.sort_pairs(fake, ctypes.c_void_p(0x2000), fake, ctypes.c_void_p(0x3000), 5, 0, None, 0,
+                          None) == N.MS_EINVAL
+    # segmented: no segments but items; one of vals_in / vals_out
+    assert lib.sort_segmented(fake, None, fake, None, None, 0, 5, 0, None, 0, None) == N.MS_EINVAL
+    assert lib.sort_segmented(fake, fake, fake, None, fake, 1, 5, 0, None, 0, None) == N.MS_EINVAL
+    assert lib.sort_segmented(None, None, None, None, None, 0, 0, 0, None, 0, None) == N.MS_OK
+    # merge: zero runs, aliasing
+    assert lib.merge_runs(fake, None, ctypes.c_void_p(0x2000), None, fake, 0, 5, 0, None, 0, None) == N.MS_EINVAL
+    assert lib.merge_runs(fake, None, fake, None, fake, 2, 5, 0, None, 0, None) == N.MS_EINVAL
+    assert "alias" in N.last_error()

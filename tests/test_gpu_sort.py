@@ -1,0 +1,212 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Integer work, so the bar is bit-exact equality with the oracle's stable sort
+on the same seeded inputs.  Sizes straddle the tile sizes (4,096 keys per
+onesweep tile for 32-bit keys, 2,048 for 64-bit; 8,192 / 4,096 keys in one
+LDS tile) and leave ragged tails.  Full-size configurations are checked by
+properties that hold at any size plus sampled rank certificates.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1105_6040_amd import api, inputs
+from tests.oracle_pins import certify_stable_sort
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 63, 64, 65, 1000, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193, 10000, 65537,
+         100003, (1 << 20) + 17]
+DISTS = ["uniform", "pos31", "small", "sorted", "reverse", "equal", "extremes", "few", "bits16"]
+DTYPES = ["i32", "u32", "u64"]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("n", SIZES)
+def test_sort_keys_parity(dt, n):
+    for dist in DISTS:
+        say(f"sort_keys {dt} n={n} {dist}")
+        k = inputs.keys(dt, n, dist, seed=n)
+        out = host(api.sort_keys(dev(k)))
+        assert np.array_equal(out, oracle.sort(k)), (dt, n, dist)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("n", SIZES)
+def test_sort_pairs_parity(dt, n):
+    for dist in ("uniform", "small", "equal", "few", "bits16", "reverse"):
+        say(f"sort_pairs {dt} n={n} {dist}")
+        k = inputs.keys(dt, n, dist, seed=n + 1)
+        v = np.arange(n, dtype=np.uint32)
+        ko, vo = api.sort_pairs(dev(k), dev(v))
+        ek, ev = oracle.sort(k, v)
+        assert np.array_equal(host(ko), ek), (dt, n, dist)
+        assert np.array_equal(host(vo), ev), (dt, n, dist)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("n", [5, 4097, 8193, 100003])
+def test_in_place(dt, n):
+    for dist in ("uniform", "small", "equal"):
+        say(f"in-place {dt} n={n} {dist}")
+        k = inputs.keys(dt, n, dist, seed=7)
+        t = dev(k)
+        api.sort_keys(t, out=t)
+        assert np.array_equal(host(t), oracle.sort(k)), (dt, n, dist)
+        v = np.arange(n, dtype=np.uint32)
+        tk, tv = dev(k), dev(v)
+        api.sort_pairs(tk, tv, keys_out=tk, vals_out=tv)
+        ek, ev = oracle.sort(k, v)
+        assert np.array_equal(host(tk), ek) and np.array_equal(host(tv), ev), (dt, n, dist)
+
+
+def test_unaligned_views():
+    base = inputs.keys("i32", 300_001, "uniform", seed=3)
+    t = dev(base)
+    for start in (1, 2, 3):
+        view = t[start:]
+        out = host(api.sort_keys(view))
+        assert np.array_equal(out, oracle.sort(base[start:])), start
+
+
+def test_deterministic_repeat():
+    k = inputs.keys("u32", 3_000_000, "few", seed=4)
+    v = np.arange(k.size, dtype=np.uint32)
+    tk, tv = dev(k), dev(v)
+    a = [host(x) for x in api.sort_pairs(tk, tv)]
+    b = [host(x) for x in api.sort_pairs(tk, tv)]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    certify_stable_sort(k, a[0], a[1])
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_sort_segmented_parity(dt):
+    g = np.random.default_rng(21)
+    for trial in range(3):
+        lengths = np.concatenate([g.integers(0, 40, 60), g.integers(8000, 8400, 6), g.integers(0, 5000, 30),
+                                  g.integers(9000, 70000, 5), [0, 1, 2]])
+        g.shuffle(lengths)
+        off = inputs.offsets_from_lengths(lengths)
+        n = int(off[-1])
+        for dist in ("uniform", "few"):
+            say(f"sort_segmented {dt} trial={trial} n={n} nseg={lengths.size} {dist}")
+            k = inputs.keys(dt, n, dist, seed=trial)
+            v = np.arange(n, dtype=np.uint32)
+            ko = api.sort_segmented(dev(k), dev(off))
+            assert np.array_equal(host(ko), oracle.sort_segmented(k, off)), (dt, trial, dist)
+            ko, vo = api.sort_segmented(dev(k), dev(off), dev(v))
+            ek, ev = oracle.sort_segmented(k, off, v)
+            assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (dt, trial, dist)
+
+
+def test_sort_segmented_in_place_and_edges():
+    k = inputs.keys("i32", 50_000, "uniform", seed=5)
+    off = np.array([0, 0, 10, 10, 20_000, 20_001, 50_000, 50_000], dtype=np.uint64)
+    t = dev(k)
+    api.sort_segmented(t, dev(off), keys_out=t)
+    assert np.array_equal(host(t), oracle.sort_segmented(k, off))
+    one = np.array([0, 50_000], dtype=np.uint64)
+    assert np.array_equal(host(api.sort_segmented(dev(k), dev(one))), oracle.sort(k))
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("nruns", [1, 2, 3, 4, 5, 8, 13, 64])
+def test_merge_runs_parity(dt, nruns):
+    g = np.random.default_rng(nruns)
+    for trial in range(2):
+        lengths = g.integers(0, 30_000, nruns)
+        if trial == 1 and nruns > 2:
+            lengths[g.integers(0, nruns, 2)] = 0
+        off = inputs.offsets_from_lengths(lengths)
+        n = int(off[-1])
+        say(f"merge_runs {dt} nruns={nruns} n={n} trial={trial}")
+        k = inputs.keys(dt, n, "small" if trial else "uniform", seed=nruns)
+        v = np.arange(n, dtype=np.uint32)
+        rk, rv = oracle.sort_segmented(k, off, v)  # sorted runs (input construction)
+        ko, vo = api.merge_runs(dev(rk), dev(off), dev(rv))
+        ek, ev = oracle.merge_runs(rk, off, rv)
+        assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (dt, nruns, trial)
+
+
+def test_paper_method_small():
+    """100,000 int32 keys, p = 4 equal parts: sort each part, merge (Figure 1)."""
+    k, p = inputs.paper_small(0)
+    off = oracle.part_offsets(k.size, p)
+    v = np.arange(k.size, dtype=np.uint32)
+    sk, sv = api.sort_segmented(dev(k), dev(off), dev(v))
+    mk, mv = api.merge_runs(sk, dev(off), sv)
+    ek, ev = oracle.paper_method(k, p, v)
+    assert np.array_equal(host(mk), ek) and np.array_equal(host(mv), ev)
+
+
+# ---------------------------------------------------------------------------- full sizes
+def fingerprint(x: np.ndarray):
+    """Sort-free multiset fingerprint: count, sum, sum of squares and xor of a
+    64-bit mix, all modulo 2^64."""
+    u = x.view(np.uint32).astype(np.uint64) if x.dtype.itemsize == 4 else x.view(np.uint64)
+    with np.errstate(over="ignore"):
+        mix = (u ^ (u >> np.uint64(29))) * np.uint64(0xBF58476D1CE4E5B9)
+        return (x.size, int(u.sum(dtype=np.uint64)), int((u * u).sum(dtype=np.uint64)),
+                int(np.bitwise_xor.reduce(mix)))
+
+
+def rank_certificate(k_in, out, samples):
+    """out[i] must be x with #(keys < x) <= i < #(keys <= x): the definition of
+    the i-th smallest key, checked per sampled position."""
+    for i in samples:
+        x = out[i]
+        less = int(np.count_nonzero(k_in < x))
+        le = int(np.count_nonzero(k_in <= x))
+        assert less <= i < le, (i, x, less, le)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "sorted", "dup"])
+def test_full_2p28_int32(dist):
+    say(f"2^28 int32 {dist}: generating")
+    k = inputs.keys_2p28(dist, seed=1)
+    say(f"2^28 int32 {dist}: sorting")
+    out = host(api.sort_keys(dev(k)))
+    say(f"2^28 int32 {dist}: checking")
+    assert np.all(out[:-1] <= out[1:]), "not non-decreasing"
+    if dist == "dup":
+        counts = np.bincount(k, minlength=1024)
+        assert np.array_equal(out, np.repeat(np.arange(1024, dtype=np.int32), counts))
+    elif dist == "sorted":
+        assert np.array_equal(out, k)
+    else:
+        assert fingerprint(out) == fingerprint(k)
+        g = np.random.default_rng(0)
+        rank_certificate(k, out, [0, k.size - 1, *g.integers(0, k.size, 6)])
+
+
+def test_full_2p26_pairs_u64():
+    say("2^26 u64 pairs: generating")
+    k, v = inputs.pairs_2p26(seed=1)
+    say("2^26 u64 pairs: sorting")
+    ko, vo = api.sort_pairs(dev(k), dev(v))
+    say("2^26 u64 pairs: certificate")
+    certify_stable_sort(k, host(ko), host(vo))
+
+
+def test_tie_dense_pairs():
+    """2^24 pairs with keys masked to 16 bits: many ties, so the value order is tested."""
+    k = inputs.keys("u64", 1 << 24, "bits16", seed=9)
+    v = np.arange(k.size, dtype=np.uint32)
+    ko, vo = api.sort_pairs(dev(k), dev(v))
+    certify_stable_sort(k, host(ko), host(vo))
