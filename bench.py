@@ -1,0 +1,251 @@
+"""Benchmark of the MI355X sort library (one GPU).
+
+Headline: a stable key-only sort of 2^28 int32 keys drawn uniformly from
+[0, 2^31) (the paper's "sort phase" for one whole list), inputs resident in
+HBM before the clock starts.  One step = one full sort_keys call.  Prints ONE
+JSON line:
+
+  value        GKeys/s over the timed steps (n * steps / elapsed)
+  roofline     the dominant kernel (the onesweep digit pass): algorithmic
+               bytes per launch (read + write of every key: 2 * n * 4 B)
+               divided by its mean duration from HIP events recorded on its
+               own stream during the timed steps, against 8 TB/s
+  cpu_baseline the CPU oracle (plain merge sort, one thread) timed on a
+               bounded sample of the same keys
+  extra        the other workloads: sorted and heavy-duplicate 2^28 int32,
+               2^26 (uint64, uint32) pairs, the paper's 10^5-key p = 4 method,
+               and a copy-kernel HBM probe
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "GKeys/s at 2^28 int32 vs HBM roofline; p50/p99 latency of batched sorts"
+DOMINANT = "onesweep_pass"
+PMC_FILE = os.path.join(ROOT, "profiles", "onesweep_pass_2p28_i32_pmc.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1105_6040_amd", "csrc", "radix.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    """Nearest-rank percentile."""
+    s = sorted(xs)
+    k = max(1, int(-(-q * len(s) // 100)))
+    return s[min(k, len(s)) - 1]
+
+
+def time_steps(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [a.elapsed_time(b) for a, b in evs]
+    return wall, per
+
+
+def source_hash(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profile(n_launch_bytes):
+    """HBM bytes per onesweep launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    try:
+        rec = json.load(open(PMC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != source_hash(KERNEL_SRC):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(keys_np, budget_s=12.0, chunk=1 << 22):
+    import oracle
+    done = 0
+    t0 = time.perf_counter()
+    chunks = 0
+    while True:
+        a = keys_np[chunks * chunk:(chunks + 1) * chunk]
+        if a.size == 0:
+            break
+        oracle.sort(a)
+        done += a.size
+        chunks += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": round(done / el / 1e9, 6), "unit": "GKeys/s", "cores": 1, "kind": "oracle",
+            "sample": f"{chunks} chunk(s) of {chunk} keys (2^22) of the same 2^28 int32 input, each "
+                      f"sorted by the single-threaded oracle merge sort; {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (no multi-GPU path is built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1105_6040_amd import _native as N
+    from paper_1105_6040_amd import api, inputs
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    n = 1 << 28
+    log("generating 2^28 int32 uniform keys")
+    keys_np = inputs.keys_2p28("uniform", seed=0)
+    keys = torch.from_numpy(keys_np).to(dev)
+    out = torch.empty_like(keys)
+    ws = torch.empty(N.workspace_size(N.MS_OP_SORT_KEYS, N.MS_KEY_I32, False, n), dtype=torch.uint8, device=dev)
+    run = lambda: api.sort_keys(keys, out=out, ws=ws)  # noqa: E731
+
+    # HBM probe: a plain device copy of the 1 GiB key array (1 GiB read + 1 GiB
+    # written).  Its duration gives achievable bandwidth; under rocprofv3 its
+    # byte counters calibrate those of the sort kernels.
+    log("copy probe")
+    _, cper = time_steps(lambda: out.copy_(keys), 5, 2, stream)
+    copy_probe = {"bytes_per_launch": 2 * n * 4, "ms_median": round(sorted(cper)[len(cper) // 2], 4),
+                  "GBps": round(2 * n * 4 / (sorted(cper)[len(cper) // 2] * 1e-3) / 1e9, 1)}
+
+    log("timing headline")
+    N.timing_reset()
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    N.timing_enable(True)
+    N.timing_reset()
+    wall, per = time_steps(run, args.steps, 0, stream)
+    N.timing_enable(False)
+    kt = N.timing_read()
+    N.timing_reset()
+    ms_per_step = wall * 1e3 / args.steps
+    value = n * args.steps / wall / 1e9
+
+    launches, total_ms = kt.get(DOMINANT, (0, 0.0))
+    mean_ms = total_ms / max(launches, 1)
+    alg_bytes = 2 * n * 4  # every key read once and written once per digit pass
+    achieved = alg_bytes / (mean_ms * 1e-3) / 1e9 if launches else None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None,
+                "traffic": traffic_from_profile(alg_bytes), "kernel": DOMINANT,
+                "mean_launch_ms": round(mean_ms, 4), "launches": launches,
+                "algorithmic_bytes_per_launch": alg_bytes}
+    kernel_ms = {k: round(v[1] / max(v[0], 1), 4) for k, v in kt.items()}
+
+    # correctness spot check of the timed output (sortedness)
+    o = out[: 1 << 20].cpu().numpy()
+    assert np.all(o[:-1] <= o[1:])
+
+    result = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GKeys/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+        "config": {"workload": "stable key-only sort of 2^28 int32 keys uniform in [0, 2^31), 1 GPU",
+                   "n": n, "key": "int32", "distribution": "uniform [0, 2^31)", "seed": 0,
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(percentile(per, 50), 4), "p99": round(percentile(per, 99), 4)},
+        "roofline": roofline,
+        "kernel_mean_ms": kernel_ms,
+        "hbm_copy_probe": copy_probe,
+    }
+    del out, ws
+    torch.cuda.empty_cache()
+
+    if not args.no_extra:
+        result["extra"] = extra_workloads(args, dev, stream, keys, keys_np)
+    if not args.no_cpu:
+        log("cpu baseline")
+        result["cpu_baseline"] = cpu_baseline(keys_np)
+    print(json.dumps(result), flush=True)
+
+
+def extra_workloads(args, dev, stream, keys_u, keys_u_np):
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1105_6040_amd import _native as N
+    from paper_1105_6040_amd import api, inputs
+
+    ex = {}
+    steps = max(5, args.steps // 2)
+
+    for dist in ("sorted", "dup"):
+        log(f"2^28 int32 {dist}")
+        k_np = inputs.keys_2p28(dist, seed=0)
+        k = torch.from_numpy(k_np).to(dev)
+        o = torch.empty_like(k)
+        ws = torch.empty(N.workspace_size(0, 0, False, k.numel()), dtype=torch.uint8, device=dev)
+        wall, per = time_steps(lambda: api.sort_keys(k, out=o, ws=ws), steps, 2, stream)
+        ex[f"keys_2p28_{dist}"] = {"GKeys_per_s": round(k.numel() * steps / wall / 1e9, 3),
+                                   "ms_median": round(sorted(per)[len(per) // 2], 4)}
+        del k, o, ws
+
+    log("2^26 u64/u32 pairs")
+    pk_np, pv_np = inputs.pairs_2p26(seed=0)
+    pk, pv = torch.from_numpy(pk_np).to(dev), torch.from_numpy(pv_np).to(dev)
+    ok, ov = torch.empty_like(pk), torch.empty_like(pv)
+    ws = torch.empty(N.workspace_size(1, 2, True, pk.numel()), dtype=torch.uint8, device=dev)
+    N.timing_enable(True)
+    N.timing_reset()
+    wall, per = time_steps(lambda: api.sort_pairs(pk, pv, ok, ov, ws=ws), steps, 2, stream)
+    N.timing_enable(False)
+    kt = N.timing_read()
+    N.timing_reset()
+    c, t = kt.get(DOMINANT, (0, 0.0))
+    pass_ms = t / max(c, 1)
+    ex["pairs_2p26_u64_u32"] = {"GPairs_per_s": round(pk.numel() * steps / wall / 1e9, 3),
+                                "ms_median": round(sorted(per)[len(per) // 2], 4),
+                                "onesweep_pass_GBps": round(2 * pk.numel() * 12 / (pass_ms * 1e-3) / 1e9, 1)
+                                if c else None}
+    del pk, pv, ok, ov, ws
+
+    log("paper method 10^5, p = 4")
+    k_np, p = inputs.paper_small(0)
+    off = oracle.part_offsets(k_np.size, p)
+    k, toff = torch.from_numpy(k_np).to(dev), torch.from_numpy(off).to(dev)
+    s_out, m_out = torch.empty_like(k), torch.empty_like(k)
+
+    def paper():
+        api.sort_segmented(k, toff, keys_out=s_out)
+        api.merge_runs(s_out, toff, keys_out=m_out)
+    wall, per = time_steps(paper, 100, 10, stream)
+    ex["paper_small_p4"] = {"us_median": round(sorted(per)[len(per) // 2] * 1e3, 1),
+                            "us_p99": round(percentile(per, 99) * 1e3, 1)}
+    assert np.array_equal(m_out.cpu().numpy(), oracle.paper_method(k_np, p))
+    return ex
+
+
+if __name__ == "__main__":
+    main()

@@ -124,6 +124,20 @@ ms_status merge_runs(const void *keys_in, const uint32_t *vals_in, void *keys_ou
 const char *ms_last_error(void);
 
 /*
+ * Launch tuning (used by the autotuner).  Values apply to calls enqueued
+ * after the change, process-wide; they never change results, only speed.
+ *   MS_TUNE_PASS_THREADS  workgroup size of the whole-list digit pass: 256,
+ *                         512 or 1024 threads of 16 keys each (tiles of
+ *                         4,096 / 8,192 / 16,384 keys).  Default 512.
+ * ms_tune_set returns MS_EINVAL for an unknown parameter or value;
+ * ms_tune_get returns the current value (0 for an unknown parameter).
+ */
+typedef enum ms_tune_param { MS_TUNE_PASS_THREADS = 0, MS_TUNE_COUNT = 1 } ms_tune_param;
+
+ms_status ms_tune_set(ms_tune_param param, int64_t value);
+int64_t ms_tune_get(ms_tune_param param);
+
+/*
  * Kernel timing (instrumentation for benchmarks).  While enabled, every
  * kernel the library enqueues is bracketed by HIP events on its own stream;
  * ms_timing_read() synchronises on those events and returns, per kernel name,

@@ -23,7 +23,9 @@ MS_KEY_I32, MS_KEY_U32, MS_KEY_U64 = 0, 1, 2
 MS_OP_SORT_KEYS, MS_OP_SORT_PAIRS, MS_OP_SORT_SEGMENTED, MS_OP_MERGE_RUNS = 0, 1, 2, 3
 
 EXPORTS = ("ms_workspace_size", "sort_keys", "sort_pairs", "sort_segmented", "merge_runs", "ms_last_error",
-           "ms_timing_enable", "ms_timing_reset", "ms_timing_read")
+           "ms_timing_enable", "ms_timing_reset", "ms_timing_read", "ms_tune_set", "ms_tune_get")
+# ms_tune_param
+MS_TUNE_PASS_THREADS = 0
 
 _lib = None
 _lock = threading.Lock()
@@ -69,6 +71,10 @@ def lib() -> ctypes.CDLL:
         L.ms_timing_reset.argtypes = []
         L.ms_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double), i32]
         L.ms_timing_read.restype = i32
+        L.ms_tune_set.argtypes = [i32, ctypes.c_int64]
+        L.ms_tune_set.restype = i32
+        L.ms_tune_get.argtypes = [i32]
+        L.ms_tune_get.restype = ctypes.c_int64
         _lib = L
         return L
 
@@ -87,6 +93,14 @@ def workspace_size(op: int, kt: int, has_values: bool, n_total: int, num_segment
     check(lib().ms_workspace_size(op, kt, int(bool(has_values)), n_total, num_segments, ctypes.byref(out)),
           "ms_workspace_size")
     return out.value
+
+
+def tune_set(param: int, value: int) -> None:
+    check(lib().ms_tune_set(param, int(value)), "ms_tune_set")
+
+
+def tune_get(param: int) -> int:
+    return int(lib().ms_tune_get(param))
 
 
 def timing_enable(on: bool) -> None:

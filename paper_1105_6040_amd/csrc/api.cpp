@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -32,7 +33,11 @@ TimingState g_timing;
 std::mutex g_timing_mu;
 
 bool valid_kt(ms_key_type kt) { return kt == MS_KEY_I32 || kt == MS_KEY_U32 || kt == MS_KEY_U64; }
+
+std::atomic<int64_t> g_tune[MS_TUNE_COUNT] = {{512}};
 }  // namespace
+
+int64_t tune_get(ms_tune_param p) { return (p >= 0 && p < MS_TUNE_COUNT) ? g_tune[p].load() : 0; }
 
 ms_status fail(ms_status st, const char* fmt, ...) {
   va_list ap;
@@ -164,6 +169,21 @@ ms_status merge_runs(const void* keys_in, const uint32_t* vals_in, void* keys_ou
   return ms::merge_sorted_runs(keys_in, vals_in, keys_out, vals_out, run_offsets, num_runs, n_total, kt, ws,
                                ws_bytes, static_cast<hipStream_t>(stream));
 }
+
+ms_status ms_tune_set(ms_tune_param p, int64_t value) {
+  switch (p) {
+    case MS_TUNE_PASS_THREADS:
+      if (value != 256 && value != 512 && value != 1024)
+        return fail(MS_EINVAL, "MS_TUNE_PASS_THREADS must be 256, 512 or 1024 (got %lld)",
+                    static_cast<long long>(value));
+      ms::g_tune[p] = value;
+      return MS_OK;
+    default:
+      return fail(MS_EINVAL, "unknown tuning parameter %d", static_cast<int>(p));
+  }
+}
+
+int64_t ms_tune_get(ms_tune_param p) { return ms::tune_get(p); }
 
 ms_status ms_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(ms::g_timing_mu);

@@ -127,6 +127,9 @@ __device__ __forceinline__ void wave_rank(const K (&keys)[KPT], int shift, uint3
     const uint32_t d = digit_of(keys[j], shift);
     const uint64_t peers = match_digit(d);
     const uint32_t old = wh[d];
+    // Every lane's read lands before any lane's write (the wave executes in
+    // lockstep; this marks the dependence for the compiler and for emulation).
+    __builtin_amdgcn_wave_barrier();
     rank[j] = old + count_below(peers);
     wh[d] = old + static_cast<uint32_t>(__popcll(peers));  // every peer stores the same value
   }
@@ -160,6 +163,41 @@ __device__ __forceinline__ uint32_t tile_digit_starts(uint32_t (*whist)[kRadix],
   }
   *count = cnt;
   return start;
+}
+
+// Decoupled look-back over the status rows of earlier tiles for one digit:
+// `st` points at this tile's word for the digit, rows are `stride` words
+// apart.  Reads kWindow predecessors at once (independent loads in flight),
+// adds AGGREGATE counts nearest-first until an INCLUSIVE count ends the walk,
+// and waits on a predecessor that has published nothing yet.  Tile 0
+// publishes INCLUSIVE directly, so the walk always ends.  Returns the
+// exclusive prefix of the digit over all earlier tiles.
+template <typename C, typename S, int kWindow = 8>
+__device__ __forceinline__ C lookback(const S* st, uint32_t tile, size_t stride) {
+  using St = Status<S>;
+  C excl = 0;
+  int64_t p = static_cast<int64_t>(tile) - 1;
+  while (true) {
+    S w[kWindow];
+#pragma unroll
+    for (int i = 0; i < kWindow; ++i)
+      w[i] = (p - i >= 0) ? status_load(st - static_cast<size_t>(static_cast<int64_t>(tile) - (p - i)) * stride)
+                          : St::kInc;
+    int used = 0;
+    bool done = false;
+#pragma unroll
+    for (int i = 0; i < kWindow; ++i) {
+      if (done || used < i) break;
+      const S flag = w[i] & St::kFlagMask;
+      if (flag == 0) break;
+      excl += static_cast<C>(w[i] & St::kValMask);
+      used = i + 1;
+      if (flag == St::kInc) done = true;
+    }
+    if (done) return excl;
+    p -= used;
+    if (used == 0) __builtin_amdgcn_s_sleep(1);
+  }
 }
 
 }  // namespace ms

@@ -31,6 +31,9 @@ ms_status check_launch(const char* name);
     if (_st != MS_OK) return _st;                                                   \
   } while (0)
 
+// Tunable launch parameters (ms_tune_set / ms_tune_get).
+int64_t tune_get(ms_tune_param p);
+
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 

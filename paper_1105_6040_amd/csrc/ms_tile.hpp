@@ -1,0 +1,136 @@
+// ms_tile.hpp -- stable in-LDS reordering of a register-resident tile by
+// 4-bit sub-digits, shared by the radix kernels.
+//
+// Layout: a tile of THREADS * KPT keys is held "blocked": thread t holds tile
+// positions t*KPT .. t*KPT+KPT-1 in its registers, in order.  A split by the
+// 4 bits at `shift` gives every key its position in the stable order of those
+// bits:
+//   1. each thread counts its own keys per bucket in one 64-bit register
+//      (16 buckets x 4-bit fields), learning for every key how many of its
+//      own earlier keys share the bucket -- no LDS traffic, no ballots;
+//   2. the per-(bucket, thread) totals go to LDS in bucket-major order and a
+//      raking block scan turns them into exclusive prefixes, so the prefix of
+//      (bucket b, thread t) counts every key of a smaller bucket plus the
+//      keys of bucket b held by threads before t;
+//   3. position = prefix[b][t] + own earlier keys of bucket b.  Equal
+//      buckets keep thread order, then register order: the split is stable.
+// Two splits (low nibble, then high nibble) order a tile by an 8-bit digit.
+#pragma once
+
+#include "ms_device.hpp"
+
+namespace ms {
+
+constexpr int kSubBits = 4;
+constexpr int kSubBuckets = 1 << kSubBits;
+
+// LDS arrays indexed in runs of 16 get one pad word per 16 entries, so that
+// both a wave reading 64 consecutive entries and a wave whose lanes each read
+// their own run of 16 hit distinct banks.
+__device__ __forceinline__ uint32_t pad16(uint32_t i) { return i + (i >> 4); }
+constexpr int padded16(int n) { return n + n / 16; }
+
+// LDS needed by tile_split for a block of THREADS threads (32-bit words).
+template <int THREADS>
+struct SplitScratch {
+  static constexpr int kCountWords = padded16(kSubBuckets * THREADS);
+};
+
+// Block-wide exclusive scan of one uint32 per thread; `scratch` holds
+// THREADS / 64 words.  Contains barriers.
+template <int THREADS>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch) {
+  constexpr int kWaves = THREADS / kWave;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const uint32_t incl = wave_inclusive_scan(v);
+  if ((tid % kWave) == kWave - 1) scratch[wave] = incl;
+  __syncthreads();
+  uint32_t base = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w)
+    if (w < wave) base += scratch[w];
+  __syncthreads();
+  return base + incl - v;
+}
+
+// Positions of the stable split of a blocked tile by bits [shift, shift+4).
+// pos[j] receives the new tile position of key j of this thread.  `counts`
+// holds SplitScratch<THREADS>::kCountWords words; `scan` THREADS/64 words.
+// Requires KPT <= 16.  Contains barriers; all threads call it.
+template <int THREADS, int KPT, typename K>
+__device__ __forceinline__ void tile_split_positions(const K (&keys)[KPT], int shift, uint32_t (&pos)[KPT],
+                                                     uint32_t* counts, uint32_t* scan) {
+  static_assert(KPT <= 16, "4-bit per-thread counters hold at most 15 earlier keys");
+  const int tid = threadIdx.x;
+
+  // 1.
+  uint64_t c = 0;
+  uint32_t bucket[KPT];
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) {
+    bucket[j] = static_cast<uint32_t>(keys[j] >> shift) & (kSubBuckets - 1);
+    const uint32_t sh = bucket[j] * kSubBits;
+    pos[j] = static_cast<uint32_t>(c >> sh) & (kSubBuckets - 1);
+    if (j + 1 < KPT) c += 1ull << sh;
+  }
+  const uint32_t last = bucket[KPT - 1];
+#pragma unroll
+  for (int b = 0; b < kSubBuckets; ++b)
+    counts[pad16(b * THREADS + tid)] = (static_cast<uint32_t>(c >> (b * kSubBits)) & (kSubBuckets - 1)) + (last == b);
+  __syncthreads();
+  uint32_t* row = counts + tid * (kSubBuckets + 1);
+  uint32_t v[kSubBuckets];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kSubBuckets; ++i) {
+    v[i] = row[i];
+    sum += v[i];
+  }
+  uint32_t run = block_exclusive_scan<THREADS>(sum, scan);
+#pragma unroll
+  for (int i = 0; i < kSubBuckets; ++i) {
+    row[i] = run;
+    run += v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) pos[j] += counts[pad16(bucket[j] * THREADS + tid)];
+  __syncthreads();  // callers may reuse `counts` (it can alias the key stage)
+}
+
+// Full stable reorder of a blocked tile by the 8-bit digit at `shift`, as two
+// 4-bit splits through `stage_k` (and `stage_v` for values), both indexed
+// through pad16 (padded16(THREADS * KPT) entries); `counts` may alias
+// stage_k.  On return the tile is in
+// digit order in the stage (entry pad16(i) holds the i-th key of the sorted
+// tile) and, if `reload` is set, back in registers in blocked layout.
+// Contains barriers.
+template <int THREADS, int KPT, bool VALS, typename K>
+__device__ __forceinline__ void tile_sort_digit(K (&keys)[KPT], uint32_t (&vals)[KPT], int shift, K* stage_k,
+                                                uint32_t* stage_v, uint32_t* counts, uint32_t* scan, bool reload) {
+  static_assert(KPT == 16, "the blocked reload assumes 16 keys per thread");
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    uint32_t pos[KPT];
+    tile_split_positions<THREADS, KPT>(keys, shift + half * kSubBits, pos, counts, scan);
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      stage_k[pad16(pos[j])] = keys[j];
+      if constexpr (VALS) stage_v[pad16(pos[j])] = vals[j];
+    }
+    __syncthreads();
+    if (half == 0 || reload) {
+      // KPT == 16: pad16(tid * 16 + j) = 17 * tid + j.
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        keys[j] = stage_k[pad16(tid * KPT + j)];
+        if constexpr (VALS) vals[j] = stage_v[pad16(tid * KPT + j)];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace ms

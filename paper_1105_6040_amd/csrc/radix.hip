@@ -25,6 +25,7 @@
 // LDS with every pass done on-chip.
 #include "ms_device.hpp"
 #include "ms_lds_sort.hpp"
+#include "ms_tile.hpp"
 #include "ms_runtime.hpp"
 
 namespace ms {
@@ -63,14 +64,16 @@ struct Buffers {
   uint32_t* alt_v;
 };
 
-// Onesweep tile geometry: 256 threads (4 waves), each wave ranks 64 x kKpt
-// keys held in registers.  Thread t owns digit t in the look-back and scans.
-template <typename K>
+// Onesweep tile geometry: THREADS threads (256, 512 or 1024; a tunable), 16
+// keys per thread held in registers.  Threads 0..255 own one digit each in
+// the look-back and scans.
+template <int THREADS>
 struct PassCfg {
-  static constexpr int kThreads = 256;
-  static constexpr int kKpt = sizeof(K) == 4 ? 16 : 8;
+  static constexpr int kThreads = THREADS;
+  static constexpr int kKpt = 16;
   static constexpr int kTile = kThreads * kKpt;
 };
+constexpr int kMinPassTile = PassCfg<256>::kTile;  // workspace is sized for the smallest tile
 
 template <typename C>
 __device__ __forceinline__ void atomic_add_c(C* p, C v) {
@@ -227,26 +230,38 @@ __global__ __launch_bounds__(256) void histogram_kernel(const K* __restrict__ ke
 
 // ---------------------------------------------------------------------------
 // 3. one onesweep digit pass.
-template <typename K, bool VALS, typename C, typename S>
-__global__ __launch_bounds__(PassCfg<K>::kThreads) void onesweep_kernel(
+//
+// Per tile: blocked load (vector loads when aligned) -> tile digit histogram
+// in LDS -> publish the tile's digit counts (AGGREGATE) at once, so later
+// tiles can look past this one while it works -> stable reorder of the tile
+// by the digit (two 4-bit splits, ms_tile.hpp) -> look back for the count of
+// each digit in all earlier tiles -> publish INCLUSIVE -> write the sorted
+// tile: entry i goes to base[d] + earlier[d] + (i - start[d]), so threads
+// i, i+1, ... write consecutive addresses inside every digit run.
+template <typename K, bool VALS, typename C, typename S, int THREADS>
+__global__ __launch_bounds__(THREADS) void onesweep_kernel(
     const SortPlan* __restrict__ plan, int pass, C n, K flip, const C* __restrict__ gbase,
     uint32_t* tile_counter, S* status_cur, S* status_next) {
-  constexpr int kThreads = PassCfg<K>::kThreads;
-  constexpr int kKpt = PassCfg<K>::kKpt;
-  constexpr int kTile = PassCfg<K>::kTile;
-  constexpr int kWaves = kThreads / kWave;
+  constexpr int kThreads = PassCfg<THREADS>::kThreads;
+  constexpr int kKpt = PassCfg<THREADS>::kKpt;
+  constexpr int kTile = PassCfg<THREADS>::kTile;
   using St = Status<S>;
 
-  __shared__ uint32_t s_whist[kWaves][kRadix];  // wave digit counts, then each wave's first slot
-  __shared__ C s_doff[kRadix];                  // output index of the tile's first key of each digit, minus its tile position
-  __shared__ K s_keys[kTile];
-  __shared__ uint32_t s_vals[VALS ? kTile : 1];
-  __shared__ uint32_t s_scan[kRadix / kWave];
+  // The split counters are dead before the first key lands in the stage, so
+  // the two share LDS.
+  constexpr int kStageBytes = padded16(kTile) * static_cast<int>(sizeof(K));
+  constexpr int kCountBytes = SplitScratch<kThreads>::kCountWords * 4;
+  __shared__ __attribute__((aligned(16))) uint8_t s_raw[kStageBytes > kCountBytes ? kStageBytes : kCountBytes];
+  K* s_stage = reinterpret_cast<K*>(s_raw);
+  uint32_t* s_counts = reinterpret_cast<uint32_t*>(s_raw);
+  __shared__ uint32_t s_vstage[VALS ? padded16(kTile) : 1];
+  __shared__ uint32_t s_hist[kRadix];
+  __shared__ C s_doff[kRadix];  // output index of the digit's first tile key, minus its tile position
+  __shared__ uint32_t s_scan[kThreads / kWave];
+  __shared__ C s_cscan[kRadix / kWave];
   __shared__ uint32_t s_tile;
 
   const int tid = threadIdx.x;
-  const int wave = tid / kWave;
-  const uint32_t lane = lane_id();
   const PassPlan& pp = plan->pass[pass];
 
   if (!pp.active) {
@@ -257,7 +272,7 @@ __global__ __launch_bounds__(PassCfg<K>::kThreads) void onesweep_kernel(
   }
 
   if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
-  for (int i = tid; i < kWaves * kRadix; i += kThreads) (&s_whist[0][0])[i] = 0;
+  for (int d = tid; d < kRadix; d += kThreads) s_hist[d] = 0;
   __syncthreads();
   const uint32_t tile = s_tile;
   if (status_next)
@@ -265,87 +280,105 @@ __global__ __launch_bounds__(PassCfg<K>::kThreads) void onesweep_kernel(
 
   const int shift = 8 * pass;
   const C tile_base = static_cast<C>(tile) * kTile;
+  const C my_base = tile_base + static_cast<C>(tid) * kKpt;
   const K* __restrict__ src = static_cast<const K*>(pp.src_k);
-  const C first = tile_base + static_cast<C>(wave * kWave * kKpt) + lane;
+  const K in_flip = pp.first ? flip : K(0);  // intermediate buffers hold encoded keys
 
-  // Load: wave w holds tile keys [w*64*kKpt, (w+1)*64*kKpt), slot j lane l
-  // is tile key w*64*kKpt + j*64 + l.  Past the end: all-ones keys, which
-  // have the largest digit in every pass and sit after every real key.
-  // Intermediate buffers hold encoded keys; only the input needs the codec.
-  const K in_flip = pp.first ? flip : K(0);
+  // Blocked load; past the end all-ones keys, which sort after every real key.
   K keys[kKpt];
-  uint32_t vals[VALS ? kKpt : 1];
+  uint32_t vals[kKpt];  // unused (and optimised away) for key-only sorts
+  const bool vec_ok = (reinterpret_cast<uintptr_t>(src) % 16 == 0) && my_base + kKpt <= n;
+  if (vec_ok) {
+    constexpr int kPer = 16 / sizeof(K);
+    const uint4* p4 = reinterpret_cast<const uint4*>(src + my_base);
 #pragma unroll
-  for (int j = 0; j < kKpt; ++j) {
-    const C idx = first + static_cast<C>(j * kWave);
-    keys[j] = idx < n ? flip_key(src[idx], in_flip) : ~K(0);
-  }
-  if constexpr (VALS) {
+    for (int q = 0; q < kKpt / kPer; ++q) {
+      const uint4 v = p4[q];
+      if constexpr (sizeof(K) == 4) {
+        keys[4 * q + 0] = v.x;
+        keys[4 * q + 1] = v.y;
+        keys[4 * q + 2] = v.z;
+        keys[4 * q + 3] = v.w;
+      } else {
+        keys[2 * q + 0] = (static_cast<uint64_t>(v.y) << 32) | v.x;
+        keys[2 * q + 1] = (static_cast<uint64_t>(v.w) << 32) | v.z;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kKpt; ++j) keys[j] = flip_key(keys[j], in_flip);
+  } else {
 #pragma unroll
     for (int j = 0; j < kKpt; ++j) {
-      const C idx = first + static_cast<C>(j * kWave);
-      vals[j] = idx < n ? pp.src_v[idx] : 0u;
+      const C idx = my_base + j;
+      keys[j] = idx < n ? flip_key(src[idx], in_flip) : ~K(0);
     }
   }
-
-  // Rank within the wave: peers by ballot, running counts in LDS.  Slots are
-  // processed in index order, lanes within a slot by lane, so equal digits
-  // get increasing ranks in input order (stability).
-  uint32_t rank[kKpt];
-  uint32_t* wh = s_whist[wave];
-  wave_rank(keys, shift, rank, wh);
-  __syncthreads();
-
-  // Per digit: tile count and the tile position of each wave's first key.
-  uint32_t cnt;
-  const uint32_t start = tile_digit_starts<kThreads>(s_whist, s_scan, &cnt);
-
-  if (tid < kRadix) {
-    // Decoupled look-back for digit `tid`.
-    S* st = status_cur + static_cast<size_t>(tile) * kRadix + tid;
-    C excl = 0;
-    if (tile == 0) {
-      status_store(st, St::kInc | static_cast<S>(cnt));
-    } else {
-      status_store(st, St::kAgg | static_cast<S>(cnt));
-      const S* q = st - kRadix;
-      while (true) {
-        const S w = status_load(q);
-        const S flag = w & St::kFlagMask;
-        if (flag == 0) {
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += static_cast<C>(w & St::kValMask);
-        if (flag == St::kInc) break;
-        q -= kRadix;
+  if constexpr (VALS) {
+    const bool vvec = (reinterpret_cast<uintptr_t>(pp.src_v) % 16 == 0) && my_base + kKpt <= n;
+    if (vvec) {
+      const uint4* p4 = reinterpret_cast<const uint4*>(pp.src_v + my_base);
+#pragma unroll
+      for (int q = 0; q < kKpt / 4; ++q) {
+        const uint4 v = p4[q];
+        vals[4 * q + 0] = v.x;
+        vals[4 * q + 1] = v.y;
+        vals[4 * q + 2] = v.z;
+        vals[4 * q + 3] = v.w;
       }
-      status_store(st, St::kInc | static_cast<S>(excl + cnt));
+    } else {
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j) {
+        const C idx = my_base + j;
+        vals[j] = idx < n ? pp.src_v[idx] : 0u;
+      }
     }
-    s_doff[tid] = gbase[tid] + excl - static_cast<C>(start);
   }
-  __syncthreads();
 
-  // Reorder the tile by digit in LDS.
+  // Tile digit histogram.
 #pragma unroll
   for (int j = 0; j < kKpt; ++j) {
-    const uint32_t pos = wh[digit_of(keys[j], shift)] + rank[j];
-    s_keys[pos] = keys[j];
-    if constexpr (VALS) s_vals[pos] = vals[j];
+    const uint32_t d = digit_of(keys[j], shift);
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    if (__builtin_amdgcn_ballot_w64(d == d0) == ~0ull) {
+      if (lane_id() == 0) atomicAdd(&s_hist[d0], static_cast<uint32_t>(kWave));
+    } else {
+      atomicAdd(&s_hist[d], 1u);
+    }
   }
   __syncthreads();
 
-  // Write digit runs: consecutive threads write consecutive addresses.
+  // Publish this tile's digit counts before sorting it.
+  S* st = status_cur + static_cast<size_t>(tile) * kRadix + tid;
+  uint32_t cnt = 0;
+  if (tid < kRadix) {
+    cnt = s_hist[tid];
+    status_store(st, (tile == 0 ? St::kInc : St::kAgg) | static_cast<S>(cnt));
+  }
+
+  tile_sort_digit<kThreads, kKpt, VALS>(keys, vals, shift, s_stage, s_vstage, s_counts, s_scan, false);
+
+  C tile_total;
+  const C start = block_exclusive_scan_radix<kThreads>(static_cast<C>(cnt), s_cscan, &tile_total);
+  if (tid < kRadix) {
+    C excl = 0;
+    if (tile != 0) {
+      excl = lookback<C, S, 16>(st, tile, kRadix);
+      status_store(st, St::kInc | static_cast<S>(excl + cnt));
+    }
+    s_doff[tid] = gbase[tid] + excl - start;
+  }
+  __syncthreads();
+
   const C remaining = n - tile_base;
   const int valid = remaining < static_cast<C>(kTile) ? static_cast<int>(remaining) : kTile;
   K* __restrict__ dst = static_cast<K*>(pp.dst_k);
   const K out_flip = pp.last ? flip : K(0);
 #pragma unroll 4
   for (int i = tid; i < valid; i += kThreads) {
-    const K k = s_keys[i];
+    const K k = s_stage[pad16(i)];
     const C o = s_doff[digit_of(k, shift)] + static_cast<C>(i);
     dst[o] = k ^ out_flip;
-    if constexpr (VALS) pp.dst_v[o] = s_vals[i];
+    if constexpr (VALS) pp.dst_v[o] = s_vstage[pad16(i)];
   }
 }
 
@@ -381,11 +414,10 @@ Layout make_layout(ms_key_type kt, bool has_vals, uint64_t n) {
     L.small = true;
     return L;  // no workspace
   }
-  const int tile = kb == 4 ? PassCfg<uint32_t>::kTile : PassCfg<uint64_t>::kTile;
   const int P = kb;
   L.big = n >= (1ull << 30);
   const size_t cb = L.big ? 8 : 4;  // counter and status word bytes
-  L.num_tiles = static_cast<uint32_t>((n + tile - 1) / tile);
+  L.num_tiles = static_cast<uint32_t>((n + kMinPassTile - 1) / kMinPassTile);
   size_t off = 0;
   L.plan = off;
   off += align_up(sizeof(SortPlan));
@@ -419,6 +451,40 @@ ms_status run_small(const void* kin, const uint32_t* vin, void* kout, uint32_t* 
   return MS_OK;
 }
 
+template <typename K, bool VALS, typename C, typename S, int THREADS>
+ms_status launch_pass_t(uint64_t n, SortPlan* plan, int p, K flip, const C* gbase, uint32_t* ctr, S* cur, S* next,
+                        hipStream_t s) {
+  const uint64_t tiles = (n + PassCfg<THREADS>::kTile - 1) / PassCfg<THREADS>::kTile;
+  MS_LAUNCH("onesweep_pass", (onesweep_kernel<K, VALS, C, S, THREADS>), static_cast<uint32_t>(tiles), THREADS, s,
+            static_cast<const SortPlan*>(plan), p, static_cast<C>(n), flip, gbase, ctr, cur, next);
+  return MS_OK;
+}
+
+// LDS bytes of one onesweep workgroup (the larger of stage and counters, plus
+// the value stage); configurations above the 160 KB of a CU fall back.
+template <typename K, bool VALS, int THREADS>
+constexpr int pass_lds_bytes() {
+  constexpr int stage = padded16(PassCfg<THREADS>::kTile) * static_cast<int>(sizeof(K));
+  constexpr int counts = SplitScratch<THREADS>::kCountWords * 4;
+  return (stage > counts ? stage : counts) + (VALS ? padded16(PassCfg<THREADS>::kTile) * 4 : 0) + 4096;
+}
+
+template <typename K, bool VALS, typename C, typename S>
+ms_status launch_pass(int threads, uint64_t n, SortPlan* plan, int p, K flip, const C* gbase, uint32_t* ctr, S* cur,
+                      S* next, hipStream_t s) {
+  switch (threads) {
+    case 1024:
+      if constexpr (pass_lds_bytes<K, VALS, 1024>() <= 160 * 1024)
+        return launch_pass_t<K, VALS, C, S, 1024>(n, plan, p, flip, gbase, ctr, cur, next, s);
+      else
+        return launch_pass_t<K, VALS, C, S, 512>(n, plan, p, flip, gbase, ctr, cur, next, s);
+    case 512:
+      return launch_pass_t<K, VALS, C, S, 512>(n, plan, p, flip, gbase, ctr, cur, next, s);
+    default:
+      return launch_pass_t<K, VALS, C, S, 256>(n, plan, p, flip, gbase, ctr, cur, next, s);
+  }
+}
+
 template <typename K, bool VALS, typename C, typename S>
 ms_status run_onesweep(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, uint64_t n, K flip,
                        char* ws, const Layout& L, hipStream_t s) {
@@ -441,11 +507,12 @@ ms_status run_onesweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   MS_LAUNCH("histogram", (histogram_kernel<K, C>), static_cast<uint32_t>(hblocks), 256, s,
             static_cast<const K*>(kin), static_cast<C>(n), flip, ghist, gbase, ctrs, plan, buf, VALS ? 1 : 0);
 
+  const int threads = static_cast<int>(tune_get(MS_TUNE_PASS_THREADS));
   for (int p = 0; p < P; ++p) {
     S* next = p + 1 < P ? status[(p + 1) & 1] : nullptr;
-    MS_LAUNCH("onesweep_pass", (onesweep_kernel<K, VALS, C, S>), L.num_tiles, PassCfg<K>::kThreads, s,
-              static_cast<const SortPlan*>(plan), p, static_cast<C>(n), flip,
-              static_cast<const C*>(gbase + p * kRadix), ctrs + 1 + p, status[p & 1], next);
+    ms_status st = launch_pass<K, VALS, C, S>(threads, n, plan, p, flip, gbase + p * kRadix, ctrs + 1 + p,
+                                              status[p & 1], next, s);
+    if (st != MS_OK) return st;
   }
   MS_LAUNCH("plan_copy", (plan_copy_kernel<K, VALS>), 1024, 256, s, static_cast<const SortPlan*>(plan), n);
   return MS_OK;

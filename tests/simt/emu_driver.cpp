@@ -1,0 +1,158 @@
+// emu_driver.cpp -- runs the library's C ABI on the CPU SIMT emulator (host
+// buffers stand in for device memory) and compares every result with the
+// CPU oracle.  Prints one line per case; exit status 1 on any mismatch.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "mi355sort.h"
+
+extern "C" {
+int oracle_sort(int kt, const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, uint64_t n);
+int oracle_sort_segmented(int kt, const void* kin, const uint32_t* vin, void* kout, uint32_t* vout,
+                          const uint64_t* off, uint64_t nseg);
+int oracle_merge_runs(int kt, const void* kin, const uint32_t* vin, void* kout, uint32_t* vout,
+                      const uint64_t* off, uint64_t nruns);
+}
+
+static uint64_t g_state = 0x9e3779b97f4a7c15ull;
+static uint64_t rnd() {  // splitmix64: input generation only
+  uint64_t z = (g_state += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+static int failures = 0;
+
+static void fill(std::vector<uint64_t>& bits, int kt, size_t n, const std::string& dist) {
+  bits.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    uint64_t r = rnd();
+    if (dist == "small") r %= 1024;
+    else if (dist == "equal") r = 12345;
+    else if (dist == "few") r = (r % 4) * 0x9e3779b97f4a7c15ull;
+    else if (dist == "sorted") r = i * 7919;
+    if (kt != MS_KEY_U64) r &= 0xffffffffull;
+    bits[i] = r;
+  }
+}
+
+template <typename K>
+static std::vector<K> narrow(const std::vector<uint64_t>& b) {
+  std::vector<K> out(b.size());
+  for (size_t i = 0; i < b.size(); ++i) out[i] = static_cast<K>(b[i]);
+  return out;
+}
+
+template <typename K>
+static void run_sort(int kt, size_t n, const std::string& dist, bool pairs, bool inplace, int threads) {
+  std::vector<uint64_t> bits;
+  fill(bits, kt, n, dist);
+  std::vector<K> kin = narrow<K>(bits), kout(n), kexp(n);
+  std::vector<uint32_t> vin(n), vout(n), vexp(n);
+  for (size_t i = 0; i < n; ++i) vin[i] = static_cast<uint32_t>(i);
+  ms_tune_set(MS_TUNE_PASS_THREADS, threads);
+  size_t wsb = 0;
+  ms_workspace_size(pairs ? MS_OP_SORT_PAIRS : MS_OP_SORT_KEYS, (ms_key_type)kt, pairs, n, 0, &wsb);
+  std::vector<char> ws(wsb + 1);
+  oracle_sort(kt, kin.data(), pairs ? vin.data() : nullptr, kexp.data(), pairs ? vexp.data() : nullptr, n);
+  K* ko = inplace ? kin.data() : kout.data();
+  uint32_t* vo = inplace ? vin.data() : vout.data();
+  ms_status st = pairs ? sort_pairs(kin.data(), vin.data(), ko, vo, n, (ms_key_type)kt, ws.data(), wsb, nullptr)
+                       : sort_keys(kin.data(), ko, n, (ms_key_type)kt, ws.data(), wsb, nullptr);
+  bool ok = st == MS_OK && memcmp(ko, kexp.data(), n * sizeof(K)) == 0 &&
+            (!pairs || memcmp(vo, vexp.data(), n * 4) == 0);
+  printf("%s %s kt=%d n=%zu dist=%s pairs=%d inplace=%d threads=%d\n", ok ? "ok  " : "FAIL",
+         pairs ? "sort_pairs" : "sort_keys", kt, n, dist.c_str(), pairs, inplace, threads);
+  fflush(stdout);
+  if (!ok) ++failures;
+}
+
+template <typename K>
+static void run_segmented(int kt, const std::vector<uint64_t>& lengths, bool pairs) {
+  std::vector<uint64_t> off(lengths.size() + 1, 0);
+  for (size_t s = 0; s < lengths.size(); ++s) off[s + 1] = off[s] + lengths[s];
+  const size_t n = off.back();
+  std::vector<uint64_t> bits;
+  fill(bits, kt, n, "few");
+  std::vector<K> kin = narrow<K>(bits), kout(n), kexp(n);
+  std::vector<uint32_t> vin(n), vout(n), vexp(n);
+  for (size_t i = 0; i < n; ++i) vin[i] = static_cast<uint32_t>(i);
+  size_t wsb = 0;
+  ms_workspace_size(MS_OP_SORT_SEGMENTED, (ms_key_type)kt, pairs, n, lengths.size(), &wsb);
+  std::vector<char> ws(wsb + 1);
+  oracle_sort_segmented(kt, kin.data(), pairs ? vin.data() : nullptr, kexp.data(), pairs ? vexp.data() : nullptr,
+                        off.data(), lengths.size());
+  ms_status st = sort_segmented(kin.data(), pairs ? vin.data() : nullptr, kout.data(), pairs ? vout.data() : nullptr,
+                                off.data(), lengths.size(), n, (ms_key_type)kt, ws.data(), wsb, nullptr);
+  bool ok = st == MS_OK && memcmp(kout.data(), kexp.data(), n * sizeof(K)) == 0 &&
+            (!pairs || memcmp(vout.data(), vexp.data(), n * 4) == 0);
+  printf("%s sort_segmented kt=%d nseg=%zu n=%zu pairs=%d\n", ok ? "ok  " : "FAIL", kt, lengths.size(), n, pairs);
+  fflush(stdout);
+  if (!ok) ++failures;
+}
+
+template <typename K>
+static void run_merge(int kt, const std::vector<uint64_t>& lengths) {
+  std::vector<uint64_t> off(lengths.size() + 1, 0);
+  for (size_t s = 0; s < lengths.size(); ++s) off[s + 1] = off[s] + lengths[s];
+  const size_t n = off.back();
+  std::vector<uint64_t> bits;
+  fill(bits, kt, n, "small");
+  std::vector<K> raw = narrow<K>(bits), kin(n), kout(n), kexp(n);
+  std::vector<uint32_t> vraw(n), vin(n), vout(n), vexp(n);
+  for (size_t i = 0; i < n; ++i) vraw[i] = static_cast<uint32_t>(i);
+  oracle_sort_segmented(kt, raw.data(), vraw.data(), kin.data(), vin.data(), off.data(), lengths.size());
+  size_t wsb = 0;
+  ms_workspace_size(MS_OP_MERGE_RUNS, (ms_key_type)kt, 1, n, lengths.size(), &wsb);
+  std::vector<char> ws(wsb + 1);
+  oracle_merge_runs(kt, kin.data(), vin.data(), kexp.data(), vexp.data(), off.data(), lengths.size());
+  ms_status st = merge_runs(kin.data(), vin.data(), kout.data(), vout.data(), off.data(), lengths.size(), n,
+                            (ms_key_type)kt, ws.data(), wsb, nullptr);
+  bool ok = st == MS_OK && memcmp(kout.data(), kexp.data(), n * sizeof(K)) == 0 &&
+            memcmp(vout.data(), vexp.data(), n * 4) == 0;
+  printf("%s merge_runs kt=%d nruns=%zu n=%zu\n", ok ? "ok  " : "FAIL", kt, lengths.size(), n);
+  fflush(stdout);
+  if (!ok) ++failures;
+}
+
+int main(int argc, char** argv) {
+  const std::string what = argc > 1 ? argv[1] : "all";
+  if (what == "quick") {  // a few cases per kernel family, for the CPU test suite
+    run_sort<uint32_t>(MS_KEY_I32, 20001, "uniform", false, false, 256);
+    run_sort<uint32_t>(MS_KEY_I32, 12000, "sorted", false, true, 512);
+    run_sort<uint64_t>(MS_KEY_U64, 9000, "few", true, false, 256);
+    run_sort<uint32_t>(MS_KEY_I32, 300, "uniform", true, false, 256);
+    run_segmented<uint32_t>(MS_KEY_I32, {0, 5, 9000, 1, 300}, true);
+    run_merge<uint32_t>(MS_KEY_U32, {3000, 0, 2500, 1});
+  }
+  if (what == "all" || what == "sort") {
+    for (int threads : {256, 512, 1024}) {
+      run_sort<uint32_t>(MS_KEY_I32, 40000, "uniform", false, false, threads);
+      run_sort<uint32_t>(MS_KEY_U32, 20001, "small", false, false, threads);
+      run_sort<uint32_t>(MS_KEY_I32, 20001, "sorted", false, false, threads);
+    }
+    run_sort<uint32_t>(MS_KEY_I32, 9000, "equal", false, false, 256);
+    run_sort<uint32_t>(MS_KEY_I32, 9000, "uniform", false, true, 256);
+    run_sort<uint32_t>(MS_KEY_U32, 12345, "few", true, false, 256);
+    run_sort<uint32_t>(MS_KEY_U32, 12345, "uniform", true, true, 512);
+    run_sort<uint64_t>(MS_KEY_U64, 10000, "uniform", false, false, 256);
+    run_sort<uint64_t>(MS_KEY_U64, 10000, "few", true, false, 512);
+    run_sort<uint32_t>(MS_KEY_I32, 100, "uniform", false, false, 256);
+  }
+  if (what == "all" || what == "segmented") {
+    run_segmented<uint32_t>(MS_KEY_I32, {0, 5, 9000, 1, 0, 8192, 8193, 300}, false);
+    run_segmented<uint32_t>(MS_KEY_U32, {7000, 10000, 3}, true);
+    run_segmented<uint64_t>(MS_KEY_U64, {5000, 4096, 4097, 0}, true);
+  }
+  if (what == "all" || what == "merge") {
+    run_merge<uint32_t>(MS_KEY_I32, {3000, 0, 2500, 4000, 1});
+    run_merge<uint64_t>(MS_KEY_U64, {1000, 2000});
+  }
+  printf("%d failure(s)\n", failures);
+  return failures ? 1 : 0;
+}
