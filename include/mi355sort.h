@@ -128,7 +128,7 @@ const char *ms_last_error(void);
  * after the change, process-wide; they never change results, only speed.
  *   MS_TUNE_PASS_THREADS  workgroup size of the whole-list digit pass: 256,
  *                         512 or 1024 threads of 16 keys each (tiles of
- *                         4,096 / 8,192 / 16,384 keys).  Default 512.
+ *                         4,096 / 8,192 / 16,384 keys).  Default 1024.
  * ms_tune_set returns MS_EINVAL for an unknown parameter or value;
  * ms_tune_get returns the current value (0 for an unknown parameter).
  */

@@ -34,7 +34,7 @@ std::mutex g_timing_mu;
 
 bool valid_kt(ms_key_type kt) { return kt == MS_KEY_I32 || kt == MS_KEY_U32 || kt == MS_KEY_U64; }
 
-std::atomic<int64_t> g_tune[MS_TUNE_COUNT] = {{512}};
+std::atomic<int64_t> g_tune[MS_TUNE_COUNT] = {{1024}};
 }  // namespace
 
 int64_t tune_get(ms_tune_param p) { return (p >= 0 && p < MS_TUNE_COUNT) ? g_tune[p].load() : 0; }
