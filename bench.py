@@ -244,7 +244,87 @@ def extra_workloads(args, dev, stream, keys_u, keys_u_np):
     ex["paper_small_p4"] = {"us_median": round(sorted(per)[len(per) // 2] * 1e3, 1),
                             "us_p99": round(percentile(per, 99) * 1e3, 1)}
     assert np.array_equal(m_out.cpu().numpy(), oracle.paper_method(k_np, p))
+    del k, toff, s_out, m_out
+
+    ex["segments_50k"] = segments_workload(dev, stream)
+    ex["serving"] = serving_workload(dev)
     return ex
+
+
+def segments_workload(dev, stream, seed=0):
+    """50,000 segments, lengths log-uniform in [16, 10^6] (about 4.5e9 int32
+    keys, uniform in [0, 2^31), drawn on the device from a seeded generator),
+    one sort_segmented call."""
+    import numpy as np
+    import torch
+
+    from paper_1105_6040_amd import _native as N
+    from paper_1105_6040_amd import api, inputs
+
+    log("segments: 50,000 log-uniform [16, 1e6]")
+    lengths = inputs.segment_lengths(seed)
+    off = inputs.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    k = torch.randint(0, 2**31, (n,), dtype=torch.int32, device=dev, generator=g)
+    toff = torch.from_numpy(off).to(dev)
+    out = torch.empty_like(k)
+    ws = torch.empty(N.workspace_size(N.MS_OP_SORT_SEGMENTED, N.MS_KEY_I32, False, n, lengths.size),
+                     dtype=torch.uint8, device=dev)
+    wall, per = time_steps(lambda: api.sort_segmented(k, toff, keys_out=out, ws=ws), 3, 1, stream)
+    ms = sorted(per)[len(per) // 2]
+    res = {"segments": int(lengths.size), "keys": n, "ms_median": round(ms, 3),
+           "GKeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
+           "GBps_at_36B_per_key": round(n * 36 / (ms * 1e-3) / 1e9, 1)}
+    del k, out, ws, toff
+    torch.cuda.empty_cache()
+    return res
+
+
+def serving_workload(dev, nreq=1000, seed=0):
+    """Serving stream: requests of (uint32 key, uint32 value) pairs, lengths
+    log-uniform in [1e3, 1e7], keys uniform, payloads staged on the device
+    before the clock.  The one-launch-per-request server's saturation rate C
+    is measured with every request arriving at once; both servers then run
+    the same Poisson trace at 0.8 C."""
+    import torch
+
+    from paper_1105_6040_amd import inputs, serve
+
+    log(f"serving: {nreq} requests")
+    arr, lengths = inputs.serving_trace(seed=seed, nreq=nreq, rate_per_s=1.0)
+    total = int(sum(int(x) for x in lengths))
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed + 5)
+    keys = torch.randint(-2**31, 2**31, (total,), dtype=torch.int32, device=dev, generator=g).view(torch.uint32)
+    vals = torch.arange(total, dtype=torch.int32, device=dev).view(torch.uint32)
+    ok, ov = torch.empty_like(keys), torch.empty_like(vals)
+    free, _ = torch.cuda.mem_get_info(dev)
+    budget = max(1 << 30, free - (16 << 30))
+
+    def serve_once(rate, batching, arrivals=None):
+        a = arrivals if arrivals is not None else [0.0] * nreq
+        reqs = serve.make_requests(a, lengths)
+        ex = serve.GpuExecutor(keys, vals, ok, ov, streams=2)
+        srv = serve.Server(ex, budget_bytes=budget, batching=batching, large_threshold=1 << 18,
+                           max_batch_pairs=1 << 24, max_inflight=4, streams=2)
+        st = srv.run(reqs)
+        torch.cuda.synchronize()
+        return st
+
+    serve_once(None, False)  # warm-up
+    sat = serve_once(None, False)
+    cap = nreq / sat.wall_s
+    rate = 0.8 * cap
+    g2 = inputs.rng("serving", seed + 1)
+    gaps = g2.exponential(1.0 / rate, nreq)
+    arrivals = list(gaps.cumsum() - gaps[0])
+    per_req = serve_once(rate, False, arrivals)
+    batched = serve_once(rate, True, arrivals)
+    return {"requests": nreq, "pairs": total, "per_request_capacity_req_per_s": round(cap, 1),
+            "rate_req_per_s": round(rate, 1), "one_launch_per_request": per_req.as_dict(),
+            "batched": batched.as_dict()}
 
 
 if __name__ == "__main__":

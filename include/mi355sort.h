@@ -129,10 +129,12 @@ const char *ms_last_error(void);
  *   MS_TUNE_PASS_THREADS  workgroup size of the whole-list digit pass: 256,
  *                         512 or 1024 threads of 16 keys each (tiles of
  *                         4,096 / 8,192 / 16,384 keys).  Default 1024.
+ *   MS_TUNE_SEG_BLOCKS    persistent workgroups of sort_segmented (1 .. 65536;
+ *                         0 = the default, 1024).
  * ms_tune_set returns MS_EINVAL for an unknown parameter or value;
  * ms_tune_get returns the current value (0 for an unknown parameter).
  */
-typedef enum ms_tune_param { MS_TUNE_PASS_THREADS = 0, MS_TUNE_COUNT = 1 } ms_tune_param;
+typedef enum ms_tune_param { MS_TUNE_PASS_THREADS = 0, MS_TUNE_SEG_BLOCKS = 1, MS_TUNE_COUNT = 2 } ms_tune_param;
 
 ms_status ms_tune_set(ms_tune_param param, int64_t value);
 int64_t ms_tune_get(ms_tune_param param);

@@ -26,6 +26,7 @@ EXPORTS = ("ms_workspace_size", "sort_keys", "sort_pairs", "sort_segmented", "me
            "ms_timing_enable", "ms_timing_reset", "ms_timing_read", "ms_tune_set", "ms_tune_get")
 # ms_tune_param
 MS_TUNE_PASS_THREADS = 0
+MS_TUNE_SEG_BLOCKS = 1
 
 _lib = None
 _lock = threading.Lock()

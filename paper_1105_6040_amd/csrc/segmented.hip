@@ -3,91 +3,190 @@
 // The scatter and sorting phases of the paper's method (Section 3.2,
 // Figure 1 steps 3-9) for many lists at once: every segment of the input is
 // sorted on its own, stably, and nothing crosses a segment boundary.  The
-// host never reads the segment offsets; each workgroup reads the ones it
-// needs, so one call costs the same few launches whatever the segment count.
+// host never reads the segment offsets, so one call is two launches whatever
+// the number and sizes of the segments:
 //
-//   short segments (at most one LDS tile): one workgroup each, every digit
-//       pass in LDS (one read and one write of HBM per key);
-//   longer segments: a persistent grid of workgroups takes segments from an
-//       atomic counter; the workgroup reads its segment once for the digit
-//       histograms of every pass, then runs each non-constant digit pass
-//       tile by tile, keeping running digit offsets in LDS (one workgroup
-//       owns the segment, so no cross-workgroup look-back is needed).
+//   1. plan (one workgroup): segment lengths -> size classes (floor log2) ->
+//      a work list of the non-empty segments, largest class first, so the
+//      longest segments start first (longest-processing-time order);
+//   2. sort (persistent workgroups): each workgroup takes the next segment
+//      of the work list from an atomic counter.  A segment of at most one
+//      tile (8,192 keys) is read once, sorted entirely in LDS (every digit
+//      pass a stable reorder by two 4-bit splits, ms_tile.hpp) and written
+//      once.  A longer segment is read once for the digit histograms of every
+//      pass; then each non-constant digit pass streams the segment tile by
+//      tile, reordering each tile in LDS and writing its digit runs at
+//      running per-digit offsets kept in LDS.  One workgroup owns the
+//      segment, so no cross-workgroup look-back is needed.
 #include "ms_device.hpp"
-#include "ms_lds_sort.hpp"
 #include "ms_runtime.hpp"
+#include "ms_tile.hpp"
 
 namespace ms {
 namespace {
 
-template <typename K>
+template <int THREADS>
 struct SegCfg {
-  static constexpr int kThreads = 256;
-  static constexpr int kKpt = sizeof(K) == 4 ? 16 : 8;
+  static constexpr int kThreads = THREADS;
+  static constexpr int kKpt = 16;
   static constexpr int kTile = kThreads * kKpt;
 };
+constexpr int kSegThreads = 512;
+constexpr int kSegTile = SegCfg<kSegThreads>::kTile;
+constexpr int kPersistentBlocks = 1024;
+constexpr int kClasses = 64;
 
-constexpr int kPersistentBlocks = 2048;
-
-__global__ void zero_words_kernel(uint32_t* p, int count) {
-  for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0;
+__device__ __forceinline__ uint64_t seg_len(const uint64_t* off, uint64_t s, uint64_t n, uint64_t* begin) {
+  uint64_t b = off[s], e = off[s + 1];
+  b = b < n ? b : n;
+  e = e < n ? e : n;
+  *begin = b;
+  return e > b ? e - b : 0;
 }
 
-template <typename K, bool VALS>
-__global__ __launch_bounds__(SegCfg<K>::kThreads) void segment_radix_kernel(
-    const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, K* alt_k, uint32_t* alt_v,
-    const uint64_t* __restrict__ off, uint64_t nseg, uint64_t n_total, K flip, uint32_t* next_seg,
-    uint64_t short_cap) {
-  constexpr int kThreads = SegCfg<K>::kThreads;
-  constexpr int kKpt = SegCfg<K>::kKpt;
-  constexpr int kTile = SegCfg<K>::kTile;
-  constexpr int kWaves = kThreads / kWave;
-  constexpr int P = sizeof(K);
+// 1. plan: work list of non-empty segments, largest size class first.
+//    ctr[0] = next work item (reset to 0), ctr[1] = number of work items.
+__global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t* __restrict__ off, uint64_t nseg,
+                                                        uint64_t n, uint32_t* worklist, uint32_t* ctr) {
+  __shared__ uint32_t s_count[kClasses];
+  __shared__ uint32_t s_base[kClasses];
+  const int tid = threadIdx.x;
+  if (tid < kClasses) s_count[tid] = 0;
+  __syncthreads();
+  for (uint64_t s = tid; s < nseg; s += blockDim.x) {
+    uint64_t b;
+    const uint64_t len = seg_len(off, s, n, &b);
+    if (len) atomicAdd(&s_count[63 - __builtin_clzll(len)], 1u);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (int c = kClasses - 1; c >= 0; --c) {
+      s_base[c] = run;
+      run += s_count[c];
+    }
+    ctr[0] = 0;
+    ctr[1] = run;
+  }
+  __syncthreads();
+  for (uint64_t s = tid; s < nseg; s += blockDim.x) {
+    uint64_t b;
+    const uint64_t len = seg_len(off, s, n, &b);
+    if (len) worklist[atomicAdd(&s_base[63 - __builtin_clzll(len)], 1u)] = static_cast<uint32_t>(s);
+  }
+}
 
-  __shared__ uint32_t s_hist[P][kRadix];       // segment digit counts per pass
-  __shared__ uint32_t s_whist[kWaves][kRadix];
-  __shared__ uint32_t s_run[kRadix];           // segment position of the next key of each digit
-  __shared__ uint32_t s_doff[kRadix];          // s_run - tile start, per digit (mod 2^32)
-  __shared__ K s_keys[kTile];
-  __shared__ uint32_t s_vals[VALS ? kTile : 1];
-  __shared__ uint32_t s_scan[kRadix / kWave];
+// Blocked load of up to one tile: thread t gets positions t*16 .. t*16+15 of
+// [base, base + valid); positions past `valid` get all-ones keys (they sort
+// after every real key) and zero values.
+template <typename K, bool VALS, int KPT>
+__device__ __forceinline__ void load_blocked(const K* src, const uint32_t* srcv, uint64_t base, int valid, K in_flip,
+                                             K (&keys)[KPT], uint32_t (&vals)[KPT]) {
+  const int first = threadIdx.x * KPT;
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) {
+    const int idx = first + j;
+    keys[j] = idx < valid ? flip_key(src[base + idx], in_flip) : ~K(0);
+    if constexpr (VALS) vals[j] = idx < valid ? srcv[base + idx] : 0u;
+  }
+}
+
+// Bits in which the first `valid` keys of a blocked tile differ from k0
+// (block-wide OR), as two 32-bit halves in `s_diff`.  Contains barriers.
+template <typename K, int KPT>
+__device__ __forceinline__ uint64_t tile_diff_bits(const K (&keys)[KPT], int valid, K k0, uint32_t* s_diff) {
+  if (threadIdx.x < 2) s_diff[threadIdx.x] = 0;
+  __syncthreads();
+  K diff = 0;
+#pragma unroll
+  for (int j = 0; j < KPT; ++j)
+    if (static_cast<int>(threadIdx.x) * KPT + j < valid) diff |= keys[j] ^ k0;
+  if (static_cast<uint32_t>(diff)) atomicOr(&s_diff[0], static_cast<uint32_t>(diff));
+  if constexpr (sizeof(K) == 8)
+    if (static_cast<uint32_t>(diff >> 32)) atomicOr(&s_diff[1], static_cast<uint32_t>(diff >> 32));
+  __syncthreads();
+  const uint64_t d = (static_cast<uint64_t>(s_diff[1]) << 32) | s_diff[0];
+  __syncthreads();
+  return d;
+}
+
+// 2. sort: persistent workgroups over the work list.
+template <typename K, bool VALS, int THREADS>
+__global__ __launch_bounds__(THREADS) void segmented_kernel(const K* kin, const uint32_t* vin, K* kout,
+                                                             uint32_t* vout, K* alt_k, uint32_t* alt_v,
+                                                             const uint64_t* __restrict__ off, uint64_t n_total,
+                                                             K flip, const uint32_t* __restrict__ worklist,
+                                                             uint32_t* ctr) {
+  constexpr int kKpt = SegCfg<THREADS>::kKpt;
+  constexpr int kTile = SegCfg<THREADS>::kTile;
+  constexpr int P = sizeof(K);
+  constexpr int kStageBytes = padded16(kTile) * static_cast<int>(sizeof(K));
+  constexpr int kCountBytes = SplitScratch<THREADS>::kCountWords * 4;
+  __shared__ __attribute__((aligned(16))) uint8_t s_raw[kStageBytes > kCountBytes ? kStageBytes : kCountBytes];
+  K* s_stage = reinterpret_cast<K*>(s_raw);
+  uint32_t* s_counts = reinterpret_cast<uint32_t*>(s_raw);
+  __shared__ uint32_t s_vstage[VALS ? padded16(kTile) : 1];
+  __shared__ uint32_t s_hist[P][kRadix];  // segment digit counts of every pass
+  __shared__ uint32_t s_thist[kRadix];    // tile digit counts
+  __shared__ uint32_t s_run[kRadix];      // segment position of the next key of each digit
+  __shared__ uint32_t s_doff[kRadix];     // s_run - tile start, per digit (mod 2^32)
+  __shared__ uint32_t s_scan[THREADS / kWave];
+  __shared__ uint32_t s_cscan[kRadix / kWave];
   __shared__ uint32_t s_diff[2];
-  __shared__ uint32_t s_seg;
+  __shared__ uint32_t s_item;
 
   const int tid = threadIdx.x;
-  const int wave = tid / kWave;
-  const uint32_t lane = lane_id();
-  const int first = wave * kWave * kKpt + static_cast<int>(lane);
   const bool inplace = kin == kout;
+  K keys[kKpt];
+  uint32_t vals[kKpt];
 
   while (true) {
     __syncthreads();
-    if (tid == 0) s_seg = atomicAdd(next_seg, 1u);
+    if (tid == 0) s_item = atomicAdd(&ctr[0], 1u);
     __syncthreads();
-    const uint64_t seg = s_seg;
-    if (seg >= nseg) return;
-    uint64_t begin = off[seg], end = off[seg + 1];
-    begin = begin < n_total ? begin : n_total;
-    end = end < n_total ? end : n_total;
-    if (end <= begin) continue;
-    const uint64_t len = end - begin;
-    if (len <= short_cap) continue;  // sorted by the in-LDS kernel
+    const uint32_t item = s_item;
+    if (item >= ctr[1]) return;
+    uint64_t begin;
+    const uint64_t len = seg_len(off, worklist[item], n_total, &begin);
+    if (len == 0) continue;
+    const K k0 = flip_key(kin[begin], flip);
 
-    // One read: digit histograms of every pass and the bits that vary.
-    for (int i = tid; i < P * kRadix; i += kThreads) (&s_hist[0][0])[i] = 0;
+    if (len <= static_cast<uint64_t>(kTile)) {
+      // ---- short segment: every pass in LDS ----
+      const int valid = static_cast<int>(len);
+      load_blocked<K, VALS>(kin, vin, begin, valid, flip, keys, vals);
+      const uint64_t diff = tile_diff_bits(keys, valid, k0, s_diff);
+      for (int p = 0; p < P; ++p) {
+        if (((diff >> (8 * p)) & (kRadix - 1)) == 0) continue;  // same for the whole block
+        tile_sort_digit<THREADS, kKpt, VALS>(keys, vals, 8 * p, s_stage, s_vstage, s_counts, s_scan, true);
+      }
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j) {
+        const int idx = tid * kKpt + j;
+        if (idx < valid) {
+          kout[begin + idx] = flip_key(keys[j], flip);
+          if constexpr (VALS) vout[begin + idx] = vals[j];
+        }
+      }
+      continue;
+    }
+
+    // ---- long segment: one read for all histograms, then tile-streamed passes ----
+    for (int i = tid; i < P * kRadix; i += THREADS) (&s_hist[0][0])[i] = 0;
     if (tid < 2) s_diff[tid] = 0;
     __syncthreads();
-    const K k0 = flip_key(kin[begin], flip);
-    K diff = 0;
-    for (uint64_t i = tid; i < len; i += kThreads) {
-      const K k = flip_key(kin[begin + i], flip);
-      diff |= k ^ k0;
+    {
+      K diff = 0;
+      for (uint64_t i = tid; i < len; i += THREADS) {
+        const K k = flip_key(kin[begin + i], flip);
+        diff |= k ^ k0;
 #pragma unroll
-      for (int p = 0; p < P; ++p) atomicAdd(&s_hist[p][digit_of(k, 8 * p)], 1u);
+        for (int p = 0; p < P; ++p) atomicAdd(&s_hist[p][digit_of(k, 8 * p)], 1u);
+      }
+      if (static_cast<uint32_t>(diff)) atomicOr(&s_diff[0], static_cast<uint32_t>(diff));
+      if constexpr (sizeof(K) == 8)
+        if (static_cast<uint32_t>(diff >> 32)) atomicOr(&s_diff[1], static_cast<uint32_t>(diff >> 32));
     }
-    if (static_cast<uint32_t>(diff)) atomicOr(&s_diff[0], static_cast<uint32_t>(diff));
-    if constexpr (sizeof(K) == 8)
-      if (static_cast<uint32_t>(diff >> 32)) atomicOr(&s_diff[1], static_cast<uint32_t>(diff >> 32));
     __syncthreads();
     const uint64_t all_diff = (static_cast<uint64_t>(s_diff[1]) << 32) | s_diff[0];
     int m = 0;
@@ -108,41 +207,37 @@ __global__ __launch_bounds__(SegCfg<K>::kThreads) void segment_radix_kernel(
       const K in_flip = (e == 0) ? flip : K(0);  // intermediate buffers hold encoded keys
 
       uint32_t total;
-      const uint32_t base = block_exclusive_scan_radix<kThreads>(tid < kRadix ? s_hist[p][tid] : 0u, s_scan, &total);
+      const uint32_t base = block_exclusive_scan_radix<THREADS>(tid < kRadix ? s_hist[p][tid] : 0u, s_cscan, &total);
       if (tid < kRadix) s_run[tid] = base;
 
       for (uint64_t t0 = 0; t0 < len; t0 += kTile) {
         const uint64_t rem = len - t0;
         const int valid = rem < static_cast<uint64_t>(kTile) ? static_cast<int>(rem) : kTile;
-        K keys[kKpt];
-        uint32_t vals[VALS ? kKpt : 1];
+        load_blocked<K, VALS>(src, srcv, begin + t0, valid, in_flip, keys, vals);
+        for (int d = tid; d < kRadix; d += THREADS) s_thist[d] = 0;
+        __syncthreads();
 #pragma unroll
         for (int j = 0; j < kKpt; ++j) {
-          const int idx = first + j * kWave;
-          keys[j] = idx < valid ? flip_key(src[begin + t0 + idx], in_flip) : ~K(0);
-          if constexpr (VALS) vals[j] = idx < valid ? srcv[begin + t0 + idx] : 0u;
+          const uint32_t d = digit_of(keys[j], shift);
+          const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+          if (__builtin_amdgcn_ballot_w64(d == d0) == ~0ull) {
+            if (lane_id() == 0) atomicAdd(&s_thist[d0], static_cast<uint32_t>(kWave));
+          } else {
+            atomicAdd(&s_thist[d], 1u);
+          }
         }
-        for (int i = tid; i < kWaves * kRadix; i += kThreads) (&s_whist[0][0])[i] = 0;
         __syncthreads();
-        uint32_t rank[kKpt];
-        wave_rank(keys, shift, rank, s_whist[wave]);
-        __syncthreads();
-        uint32_t cnt;
-        const uint32_t start = tile_digit_starts<kThreads>(s_whist, s_scan, &cnt);
+        const uint32_t cnt = tid < kRadix ? s_thist[tid] : 0u;
+        tile_sort_digit<THREADS, kKpt, VALS>(keys, vals, shift, s_stage, s_vstage, s_counts, s_scan, false);
+        uint32_t tile_total;
+        const uint32_t start = block_exclusive_scan_radix<THREADS>(cnt, s_cscan, &tile_total);
         if (tid < kRadix) s_doff[tid] = s_run[tid] - start;
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kKpt; ++j) {
-          const uint32_t pos = s_whist[wave][digit_of(keys[j], shift)] + rank[j];
-          s_keys[pos] = keys[j];
-          if constexpr (VALS) s_vals[pos] = vals[j];
-        }
-        __syncthreads();
-        for (int i = tid; i < valid; i += kThreads) {
-          const K k = s_keys[i];
+        for (int i = tid; i < valid; i += THREADS) {
+          const K k = s_stage[pad16(i)];
           const uint64_t o = begin + static_cast<uint32_t>(s_doff[digit_of(k, shift)] + static_cast<uint32_t>(i));
           dst[o] = k ^ out_flip;
-          if constexpr (VALS) dstv[o] = s_vals[i];
+          if constexpr (VALS) dstv[o] = s_vstage[pad16(i)];
         }
         __syncthreads();
         if (tid < kRadix) s_run[tid] += cnt;
@@ -166,7 +261,7 @@ __global__ __launch_bounds__(SegCfg<K>::kThreads) void segment_radix_kernel(
       csrcv = alt_v;
     }
     if (csrc) {
-      for (uint64_t i = tid; i < len; i += kThreads) {
+      for (uint64_t i = tid; i < len; i += THREADS) {
         kout[begin + i] = csrc[begin + i];
         if constexpr (VALS) vout[begin + i] = csrcv[begin + i];
       }
@@ -175,14 +270,16 @@ __global__ __launch_bounds__(SegCfg<K>::kThreads) void segment_radix_kernel(
 }
 
 struct SegLayout {
-  size_t ctr = 0, alt_k = 0, alt_v = 0, total = 0;
+  size_t ctr = 0, worklist = 0, alt_k = 0, alt_v = 0, total = 0;
 };
 
-SegLayout seg_layout(ms_key_type kt, bool has_vals, uint64_t n) {
+SegLayout seg_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg) {
   SegLayout L;
   size_t off = 0;
   L.ctr = off;
   off += kAlign;
+  L.worklist = off;
+  off += align_up(nseg * sizeof(uint32_t));
   L.alt_k = off;
   off += align_up(n * key_bytes(kt));
   if (has_vals) {
@@ -197,31 +294,30 @@ template <typename K, bool VALS>
 ms_status run_segmented(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
                         uint64_t nseg, uint64_t n, K flip, char* ws, const SegLayout& L, hipStream_t s) {
   uint32_t* ctr = reinterpret_cast<uint32_t*>(ws + L.ctr);
+  uint32_t* worklist = reinterpret_cast<uint32_t*>(ws + L.worklist);
   K* alt_k = reinterpret_cast<K*>(ws + L.alt_k);
   uint32_t* alt_v = VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr;
-  MS_LAUNCH("seg_clear", zero_words_kernel, 1, 64, s, ctr, 1);
-  MS_LAUNCH("seg_lds_sort", (lds_sort_kernel<K, VALS>), static_cast<uint32_t>(nseg), LdsCfg<K>::kThreads, s,
-            static_cast<const K*>(kin), vin, static_cast<K*>(kout), vout, off,
-            static_cast<const uint32_t*>(nullptr), n, flip);
-  const uint32_t blocks = static_cast<uint32_t>(nseg < kPersistentBlocks ? nseg : kPersistentBlocks);
-  MS_LAUNCH("seg_radix", (segment_radix_kernel<K, VALS>), blocks, SegCfg<K>::kThreads, s,
-            static_cast<const K*>(kin), vin, static_cast<K*>(kout), vout, alt_k, alt_v, off, nseg, n, flip, ctr,
-            static_cast<uint64_t>(LdsCfg<K>::kTile));
+  MS_LAUNCH("seg_plan", seg_plan_kernel, 1, 1024, s, off, nseg, n, worklist, ctr);
+  int64_t want = tune_get(MS_TUNE_SEG_BLOCKS);
+  if (want <= 0) want = kPersistentBlocks;
+  const uint32_t blocks = static_cast<uint32_t>(nseg < static_cast<uint64_t>(want) ? nseg : want);
+  MS_LAUNCH("seg_sort", (segmented_kernel<K, VALS, kSegThreads>), blocks, kSegThreads, s,
+            static_cast<const K*>(kin), vin, static_cast<K*>(kout), vout, alt_k, alt_v, off, n, flip,
+            static_cast<const uint32_t*>(worklist), ctr);
   return MS_OK;
 }
 
 }  // namespace
 
 size_t segmented_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg) {
-  (void)nseg;
-  return seg_layout(kt, has_vals, n).total;
+  return seg_layout(kt, has_vals, n, nseg).total;
 }
 
 ms_status segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
                          const uint64_t* offsets, uint64_t nseg, uint64_t n, ms_key_type kt, void* ws,
                          size_t ws_bytes, hipStream_t s) {
   const bool vals = vals_in != nullptr;
-  const SegLayout L = seg_layout(kt, vals, n);
+  const SegLayout L = seg_layout(kt, vals, n, nseg);
   if (ws_bytes < L.total || !ws)
     return fail(MS_EINVAL, "sort_segmented: workspace too small: %zu bytes given, %zu needed", ws_bytes, L.total);
   if (nseg > 0x7fffffffull) return fail(MS_ENOTSUP, "sort_segmented: at most 2^31-1 segments per call");

@@ -144,8 +144,9 @@ int main(int argc, char** argv) {
     run_sort<uint64_t>(MS_KEY_U64, 10000, "few", true, false, 512);
     run_sort<uint32_t>(MS_KEY_I32, 100, "uniform", false, false, 256);
   }
-  if (what == "all" || what == "segmented") {
+  if (what == "all" || what == "segmented" || what == "seg") {
     run_segmented<uint32_t>(MS_KEY_I32, {0, 5, 9000, 1, 0, 8192, 8193, 300}, false);
+    run_segmented<uint32_t>(MS_KEY_I32, {20000, 17, 16, 4000, 0, 1}, true);
     run_segmented<uint32_t>(MS_KEY_U32, {7000, 10000, 3}, true);
     run_segmented<uint64_t>(MS_KEY_U64, {5000, 4096, 4097, 0}, true);
   }
