@@ -129,6 +129,8 @@ const char *ms_last_error(void);
  *   MS_TUNE_PASS_THREADS  workgroup size of the whole-list digit pass: 256,
  *                         512 or 1024 threads of 16 keys each (tiles of
  *                         4,096 / 8,192 / 16,384 keys).  Default 1024.
+ *                         1024 applies to 32-bit keys without values; other
+ *                         sorts use 512 when 1024 is set.
  *   MS_TUNE_SEG_BLOCKS    persistent workgroups of sort_segmented (1 .. 65536;
  *                         0 = the default, 1024).
  * ms_tune_set returns MS_EINVAL for an unknown parameter or value;

@@ -469,12 +469,20 @@ constexpr int pass_lds_bytes() {
   return (stage > counts ? stage : counts) + (VALS ? padded16(PassCfg<THREADS>::kTile) * 4 : 0) + 4096;
 }
 
+// 1,024-thread tiles are used for 32-bit keys without values only: the other
+// forms need more than the 128 VGPRs a 1,024-thread workgroup may hold and
+// would run with register spills, so they take 512-thread tiles.
+template <typename K, bool VALS>
+constexpr bool pass_1024_ok() {
+  return sizeof(K) == 4 && !VALS && pass_lds_bytes<K, VALS, 1024>() <= 160 * 1024;
+}
+
 template <typename K, bool VALS, typename C, typename S>
 ms_status launch_pass(int threads, uint64_t n, SortPlan* plan, int p, K flip, const C* gbase, uint32_t* ctr, S* cur,
                       S* next, hipStream_t s) {
   switch (threads) {
     case 1024:
-      if constexpr (pass_lds_bytes<K, VALS, 1024>() <= 160 * 1024)
+      if constexpr (pass_1024_ok<K, VALS>())
         return launch_pass_t<K, VALS, C, S, 1024>(n, plan, p, flip, gbase, ctr, cur, next, s);
       else
         return launch_pass_t<K, VALS, C, S, 512>(n, plan, p, flip, gbase, ctr, cur, next, s);

@@ -75,6 +75,9 @@ class Executor:
     def release(self, handle) -> None:
         pass
 
+    def join(self) -> None:
+        """Order the caller's later work after every launch (device executors)."""
+
 
 @dataclasses.dataclass
 class ServeStats:
@@ -187,6 +190,7 @@ class Server:
                 wait = reqs[i].arrival - (self.clock() - t0)
                 if wait > 0:
                     time.sleep(min(wait, 0.001))
+        self.ex.join()
         wall = max(r.done for r in reqs) - min(r.arrival for r in reqs)
         return ServeStats([r.latency * 1e3 for r in reqs], sum(r.n for r in reqs), wall, launches, max_seen, waits,
                           max_used)
@@ -244,6 +248,17 @@ class GpuExecutor(Executor):
         self.keys, self.vals, self.out_k, self.out_v = keys, vals, out_k, out_v
         self.device = keys.device
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
+        # The payload and output buffers were produced on the caller's stream;
+        # the launch streams do not synchronise with it by themselves.
+        caller = torch.cuda.current_stream(self.device)
+        for st in self.streams:
+            st.wait_stream(caller)
+
+    def join(self) -> None:
+        """Make the caller's stream wait for everything launched so far."""
+        caller = self.torch.cuda.current_stream(self.device)
+        for st in self.streams:
+            caller.wait_stream(st)
 
     def workspace_bytes(self, pairs: int, segments: int) -> int:
         N = self.N

@@ -36,6 +36,7 @@ static void fill(std::vector<uint64_t>& bits, int kt, size_t n, const std::strin
     else if (dist == "equal") r = 12345;
     else if (dist == "few") r = (r % 4) * 0x9e3779b97f4a7c15ull;
     else if (dist == "sorted") r = i * 7919;
+    else if (dist == "low12") r &= 0xfff;
     if (kt != MS_KEY_U64) r &= 0xffffffffull;
     bits[i] = r;
   }
@@ -73,12 +74,12 @@ static void run_sort(int kt, size_t n, const std::string& dist, bool pairs, bool
 }
 
 template <typename K>
-static void run_segmented(int kt, const std::vector<uint64_t>& lengths, bool pairs) {
+static void run_segmented(int kt, const std::vector<uint64_t>& lengths, bool pairs, const char* dist = "few") {
   std::vector<uint64_t> off(lengths.size() + 1, 0);
   for (size_t s = 0; s < lengths.size(); ++s) off[s + 1] = off[s] + lengths[s];
   const size_t n = off.back();
   std::vector<uint64_t> bits;
-  fill(bits, kt, n, "few");
+  fill(bits, kt, n, dist);
   std::vector<K> kin = narrow<K>(bits), kout(n), kexp(n);
   std::vector<uint32_t> vin(n), vout(n), vexp(n);
   for (size_t i = 0; i < n; ++i) vin[i] = static_cast<uint32_t>(i);
@@ -91,7 +92,8 @@ static void run_segmented(int kt, const std::vector<uint64_t>& lengths, bool pai
                                 off.data(), lengths.size(), n, (ms_key_type)kt, ws.data(), wsb, nullptr);
   bool ok = st == MS_OK && memcmp(kout.data(), kexp.data(), n * sizeof(K)) == 0 &&
             (!pairs || memcmp(vout.data(), vexp.data(), n * 4) == 0);
-  printf("%s sort_segmented kt=%d nseg=%zu n=%zu pairs=%d\n", ok ? "ok  " : "FAIL", kt, lengths.size(), n, pairs);
+  printf("%s sort_segmented kt=%d nseg=%zu n=%zu pairs=%d dist=%s\n", ok ? "ok  " : "FAIL", kt, lengths.size(), n, pairs,
+         dist);
   fflush(stdout);
   if (!ok) ++failures;
 }
@@ -143,6 +145,10 @@ int main(int argc, char** argv) {
     run_sort<uint64_t>(MS_KEY_U64, 10000, "uniform", false, false, 256);
     run_sort<uint64_t>(MS_KEY_U64, 10000, "few", true, false, 512);
     run_sort<uint32_t>(MS_KEY_I32, 100, "uniform", false, false, 256);
+  }
+  if (what == "low12") {
+    run_segmented<uint32_t>(MS_KEY_U32, {18599, 3000, 1200, 40000}, true, "low12");
+    run_sort<uint32_t>(MS_KEY_U32, 18599, "low12", true, false, 1024);
   }
   if (what == "all" || what == "segmented" || what == "seg") {
     run_segmented<uint32_t>(MS_KEY_I32, {0, 5, 9000, 1, 0, 8192, 8193, 300}, false);

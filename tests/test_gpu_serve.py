@@ -47,8 +47,19 @@ def test_serving_results_alone_and_in_the_mix(batching):
         a, b = r.offset, r.offset + r.n
         ak, av = api.sort_pairs(tk[a:b], tv[a:b])
         torch.cuda.synchronize()
-        assert np.array_equal(out_k[a:b], ak.cpu().numpy()), r.rid
-        assert np.array_equal(out_v[a:b], av.cpu().numpy()), r.rid
+        ak, av = ak.cpu().numpy(), av.cpu().numpy()
+        if not (np.array_equal(out_k[a:b], ak) and np.array_equal(out_v[a:b], av)):
+            ek, ev = oracle.sort(keys[a:b], vals[a:b])
+            bad = np.nonzero((out_k[a:b] != ek) | (out_v[a:b] != ev))[0]
+            say(f"request {r.rid} n={r.n} path={r.path}: served==oracle {bad.size == 0}, "
+                f"alone==oracle {np.array_equal(ak, ek) and np.array_equal(av, ev)}, "
+                f"served mismatches {bad.size} first {bad[:8].tolist()} "
+                f"served keys sorted {bool(np.all(out_k[a:b][1:] >= out_k[a:b][:-1]))}")
+            if bad.size:
+                i = int(bad[0])
+                say(f"  at {i}: served {out_k[a+i]}/{out_v[a+i]} oracle {ek[i]}/{ev[i]}")
+        assert np.array_equal(out_k[a:b], ak), r.rid
+        assert np.array_equal(out_v[a:b], av), r.rid
     for r in reqs[::16]:
         a, b = r.offset, r.offset + r.n
         ek, ev = oracle.sort(keys[a:b], vals[a:b])

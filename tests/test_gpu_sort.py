@@ -76,6 +76,39 @@ def test_in_place(dt, n):
         assert np.array_equal(host(tk), ek) and np.array_equal(host(tv), ev), (dt, n, dist)
 
 
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_every_tile_size(threads):
+    from paper_1105_6040_amd import _native as N
+    old = N.tune_get(N.MS_TUNE_PASS_THREADS)
+    N.tune_set(N.MS_TUNE_PASS_THREADS, threads)
+    try:
+        for dt in DTYPES:
+            for n in (9000, 16383, 16385, 18599, 40000, 300_001):
+                for dist in ("uniform", "small", "bits16"):
+                    say(f"tile threads={threads} {dt} n={n} {dist}")
+                    k = inputs.keys(dt, n, dist, seed=n + threads)
+                    v = np.arange(n, dtype=np.uint32)
+                    assert np.array_equal(host(api.sort_keys(dev(k))), oracle.sort(k)), (threads, dt, n, dist)
+                    ko, vo = api.sort_pairs(dev(k), dev(v))
+                    ek, ev = oracle.sort(k, v)
+                    assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (threads, dt, n, dist)
+    finally:
+        N.tune_set(N.MS_TUNE_PASS_THREADS, old)
+
+
+def test_repeat_determinism_low_bits():
+    """The same pairs sorted 25 times give the oracle's answer every time
+    (12-bit keys: two constant digit bytes, many ties)."""
+    g = np.random.default_rng(7)
+    k = (g.integers(0, 2**32, 18599, dtype=np.uint32) & np.uint32(0xFFF)).astype(np.uint32)
+    v = np.arange(k.size, dtype=np.uint32)
+    ek, ev = oracle.sort(k, v)
+    tk, tv = dev(k), dev(v)
+    for rep in range(25):
+        ko, vo = api.sort_pairs(tk, tv)
+        assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), rep
+
+
 def test_unaligned_views():
     base = inputs.keys("i32", 300_001, "uniform", seed=3)
     t = dev(base)
