@@ -138,6 +138,10 @@ def main():
     copy_probe = {"bytes_per_launch": 2 * n * 4, "ms_median": round(sorted(cper)[len(cper) // 2], 4),
                   "GBps": round(2 * n * 4 / (sorted(cper)[len(cper) // 2] * 1e-3) / 1e9, 1)}
 
+    log("autotuning the headline sort")
+    from paper_1105_6040_amd import tune
+    tuner = tune.Tuner(cache_path=None, reps=3)
+    tuned = tuner.tune_sort(keys)
     log("timing headline")
     N.timing_reset()
     for _ in range(args.warmup):
@@ -178,6 +182,8 @@ def main():
         "roofline": roofline,
         "kernel_mean_ms": kernel_ms,
         "hbm_copy_probe": copy_probe,
+        "tuning": {"pass_threads": tuned["params"][0], "hist_blocks": tuned["params"][1],
+                   "trials_ms": tuned["trials"]},
     }
     del out, ws
     torch.cuda.empty_cache()
@@ -272,9 +278,11 @@ def segments_workload(dev, stream, seed=0):
     out = torch.empty_like(k)
     ws = torch.empty(N.workspace_size(N.MS_OP_SORT_SEGMENTED, N.MS_KEY_I32, False, n, lengths.size),
                      dtype=torch.uint8, device=dev)
+    from paper_1105_6040_amd import tune
+    tuned = tune.Tuner(cache_path=None, reps=1).tune_segmented(k, toff)
     wall, per = time_steps(lambda: api.sort_segmented(k, toff, keys_out=out, ws=ws), 3, 1, stream)
     ms = sorted(per)[len(per) // 2]
-    res = {"segments": int(lengths.size), "keys": n, "ms_median": round(ms, 3),
+    res = {"segments": int(lengths.size), "keys": n, "ms_median": round(ms, 3), "seg_blocks": tuned["params"][0],
            "GKeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
            "GBps_at_36B_per_key": round(n * 36 / (ms * 1e-3) / 1e9, 1)}
     del k, out, ws, toff
@@ -303,28 +311,32 @@ def serving_workload(dev, nreq=1000, seed=0):
     free, _ = torch.cuda.mem_get_info(dev)
     budget = max(1 << 30, free - (16 << 30))
 
-    def serve_once(rate, batching, arrivals=None):
+    def serve_once(batching, arrivals=None, threshold=1 << 18):
         a = arrivals if arrivals is not None else [0.0] * nreq
         reqs = serve.make_requests(a, lengths)
         ex = serve.GpuExecutor(keys, vals, ok, ov, streams=2)
-        srv = serve.Server(ex, budget_bytes=budget, batching=batching, large_threshold=1 << 18,
+        srv = serve.Server(ex, budget_bytes=budget, batching=batching, large_threshold=threshold,
                            max_batch_pairs=1 << 24, max_inflight=4, streams=2)
         st = srv.run(reqs)
         torch.cuda.synchronize()
         return st
 
-    serve_once(None, False)  # warm-up
-    sat = serve_once(None, False)
+    serve_once(False)  # warm-up
+    sat = serve_once(False)
     cap = nreq / sat.wall_s
     rate = 0.8 * cap
     g2 = inputs.rng("serving", seed + 1)
     gaps = g2.exponential(1.0 / rate, nreq)
     arrivals = list(gaps.cumsum() - gaps[0])
-    per_req = serve_once(rate, False, arrivals)
-    batched = serve_once(rate, True, arrivals)
+    from paper_1105_6040_amd import tune
+    tuned = tune.Tuner(cache_path=None).tune_serving(lambda t: serve_once(True, arrivals, t))
+    threshold = tuned["params"][0]
+    per_req = serve_once(False, arrivals)
+    batched = serve_once(True, arrivals, threshold)
     return {"requests": nreq, "pairs": total, "per_request_capacity_req_per_s": round(cap, 1),
-            "rate_req_per_s": round(rate, 1), "one_launch_per_request": per_req.as_dict(),
-            "batched": batched.as_dict()}
+            "rate_req_per_s": round(rate, 1), "batch_threshold_pairs": threshold,
+            "threshold_trials_p99_p50_ms": tuned["trials"],
+            "one_launch_per_request": per_req.as_dict(), "batched": batched.as_dict()}
 
 
 if __name__ == "__main__":

@@ -133,10 +133,17 @@ const char *ms_last_error(void);
  *                         sorts use 512 when 1024 is set.
  *   MS_TUNE_SEG_BLOCKS    persistent workgroups of sort_segmented (1 .. 65536;
  *                         0 = the default, 1024).
+ *   MS_TUNE_HIST_BLOCKS   workgroups of the digit-histogram read of sort_keys /
+ *                         sort_pairs (1 .. 65536; 0 = the default, 1024).
  * ms_tune_set returns MS_EINVAL for an unknown parameter or value;
  * ms_tune_get returns the current value (0 for an unknown parameter).
  */
-typedef enum ms_tune_param { MS_TUNE_PASS_THREADS = 0, MS_TUNE_SEG_BLOCKS = 1, MS_TUNE_COUNT = 2 } ms_tune_param;
+typedef enum ms_tune_param {
+    MS_TUNE_PASS_THREADS = 0,
+    MS_TUNE_SEG_BLOCKS = 1,
+    MS_TUNE_HIST_BLOCKS = 2,
+    MS_TUNE_COUNT = 3
+} ms_tune_param;
 
 ms_status ms_tune_set(ms_tune_param param, int64_t value);
 int64_t ms_tune_get(ms_tune_param param);

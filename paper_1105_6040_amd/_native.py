@@ -27,6 +27,7 @@ EXPORTS = ("ms_workspace_size", "sort_keys", "sort_pairs", "sort_segmented", "me
 # ms_tune_param
 MS_TUNE_PASS_THREADS = 0
 MS_TUNE_SEG_BLOCKS = 1
+MS_TUNE_HIST_BLOCKS = 2
 
 _lib = None
 _lock = threading.Lock()

@@ -133,4 +133,84 @@ __device__ __forceinline__ void tile_sort_digit(K (&keys)[KPT], uint32_t (&vals)
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same reorder for one wave on its own (64 lanes x KPT keys): used to sort
+// many short lists at once, one per wave.  Lanes exchange data through the
+// wave's own LDS slice; the wave executes LDS instructions in order, so a
+// wave-scope fence (which also keeps the compiler from reordering) replaces
+// the block barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// LDS words of one wave's split counters (aliasing its key stage is fine).
+constexpr int kWaveCountWords = padded16(kSubBuckets * kWave);
+
+template <int KPT, typename K>
+__device__ __forceinline__ void wave_split_positions(const K (&keys)[KPT], int shift, uint32_t (&pos)[KPT],
+                                                     uint32_t* counts) {
+  static_assert(KPT <= 16, "4-bit per-thread counters hold at most 15 earlier keys");
+  const uint32_t lane = lane_id();
+  uint64_t c = 0;
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) {
+    const uint32_t sh = (static_cast<uint32_t>(keys[j] >> shift) & (kSubBuckets - 1)) * kSubBits;
+    pos[j] = static_cast<uint32_t>(c >> sh) & (kSubBuckets - 1);
+    if (j + 1 < KPT) c += 1ull << sh;
+  }
+  const uint32_t last = static_cast<uint32_t>(keys[KPT - 1] >> shift) & (kSubBuckets - 1);
+  constexpr uint32_t kRow = kWave * 17 / 16;  // padded row of 64 entries
+  uint32_t* mine = counts + pad16(lane);
+#pragma unroll
+  for (int b = 0; b < kSubBuckets; ++b)
+    mine[b * kRow] = (static_cast<uint32_t>(c >> (b * kSubBits)) & (kSubBuckets - 1)) + (last == b);
+  wave_sync();
+  uint32_t* row = counts + lane * (kSubBuckets + 1);  // = pad16(lane * 16)
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kSubBuckets; ++i) sum += row[i];
+  uint32_t run = wave_inclusive_scan(sum) - sum;
+#pragma unroll
+  for (int i = 0; i < kSubBuckets; ++i) {
+    const uint32_t v = row[i];
+    row[i] = run;
+    run += v;
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) pos[j] += mine[(static_cast<uint32_t>(keys[j] >> shift) & (kSubBuckets - 1)) * kRow];
+  wave_sync();
+}
+
+// Stable reorder of one wave's blocked tile (64 x KPT keys) by the 8-bit
+// digit at `shift`; stage_k / stage_v are the wave's own padded16(64 * KPT)
+// entry slices and `counts` may alias stage_k.  Keys return in registers in
+// blocked layout.
+template <int KPT, bool VALS, typename K>
+__device__ __forceinline__ void wave_sort_digit(K (&keys)[KPT], uint32_t (&vals)[KPT], int shift, K* stage_k,
+                                                uint32_t* stage_v, uint32_t* counts) {
+  static_assert(KPT == 16, "the blocked reload assumes 16 keys per lane");
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    uint32_t pos[KPT];
+    wave_split_positions<KPT>(keys, shift + half * kSubBits, pos, counts);
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      stage_k[pad16(pos[j])] = keys[j];
+      if constexpr (VALS) stage_v[pad16(pos[j])] = vals[j];
+    }
+    wave_sync();
+    const K* my_k = stage_k + 17 * lane;
+    const uint32_t* my_v = stage_v + 17 * lane;
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      keys[j] = my_k[j];
+      if constexpr (VALS) vals[j] = my_v[j];
+    }
+    wave_sync();
+  }
+}
+
 }  // namespace ms

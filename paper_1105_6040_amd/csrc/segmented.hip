@@ -10,10 +10,12 @@
 //      a work list of the non-empty segments, largest class first, so the
 //      longest segments start first (longest-processing-time order);
 //   2. sort (persistent workgroups): each workgroup takes the next segment
-//      of the work list from an atomic counter.  A segment of at most one
-//      tile (8,192 keys) is read once, sorted entirely in LDS (every digit
-//      pass a stable reorder by two 4-bit splits, ms_tile.hpp) and written
-//      once.  A longer segment is read once for the digit histograms of every
+//      of the work list from an atomic counter.  Segments of fewer than 1,024
+//      keys are taken eight at a time, one per wave, and each wave sorts its
+//      segment alone in its slice of LDS.  A segment of at most one tile
+//      (8,192 keys) is read once, sorted entirely in LDS by the workgroup
+//      (every digit pass a stable reorder by two 4-bit splits, ms_tile.hpp)
+//      and written once.  A longer segment is read once for the digit histograms of every
 //      pass; then each non-constant digit pass streams the segment tile by
 //      tile, reordering each tile in LDS and writing its digit runs at
 //      running per-digit offsets kept in LDS.  One workgroup owns the
@@ -35,6 +37,8 @@ constexpr int kSegThreads = 512;
 constexpr int kSegTile = SegCfg<kSegThreads>::kTile;
 constexpr int kPersistentBlocks = 1024;
 constexpr int kClasses = 64;
+constexpr int kTinyClass = 9;  // floor(log2 len) <= 9: fewer than 1,024 keys, one wave
+constexpr int kTinyKeys = kWave * 16;
 
 __device__ __forceinline__ uint64_t seg_len(const uint64_t* off, uint64_t s, uint64_t n, uint64_t* begin) {
   uint64_t b = off[s], e = off[s + 1];
@@ -45,7 +49,8 @@ __device__ __forceinline__ uint64_t seg_len(const uint64_t* off, uint64_t s, uin
 }
 
 // 1. plan: work list of non-empty segments, largest size class first.
-//    ctr[0] = next work item (reset to 0), ctr[1] = number of work items.
+//    ctr[0] = next work item (reset to 0), ctr[1] = number of work items,
+//    ctr[2] = first item of the wave-sized class, ctr[3] = next such item.
 __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t* __restrict__ off, uint64_t nseg,
                                                         uint64_t n, uint32_t* worklist, uint32_t* ctr) {
   __shared__ uint32_t s_count[kClasses];
@@ -60,13 +65,16 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t* __restri
   }
   __syncthreads();
   if (tid == 0) {
-    uint32_t run = 0;
+    uint32_t run = 0, tiny_begin = 0;
     for (int c = kClasses - 1; c >= 0; --c) {
+      if (c == kTinyClass) tiny_begin = run;
       s_base[c] = run;
       run += s_count[c];
     }
     ctr[0] = 0;
     ctr[1] = run;
+    ctr[2] = tiny_begin;
+    ctr[3] = tiny_begin;
   }
   __syncthreads();
   for (uint64_t s = tid; s < nseg; s += blockDim.x) {
@@ -135,16 +143,69 @@ __global__ __launch_bounds__(THREADS) void segmented_kernel(const K* kin, const 
   __shared__ uint32_t s_diff[2];
   __shared__ uint32_t s_item;
 
+  __shared__ uint32_t s_mode;
   const int tid = threadIdx.x;
   const bool inplace = kin == kout;
   K keys[kKpt];
   uint32_t vals[kKpt];
+  constexpr int kWaves = THREADS / kWave;
 
   while (true) {
     __syncthreads();
-    if (tid == 0) s_item = atomicAdd(&ctr[0], 1u);
+    if (tid == 0) {
+      const uint32_t i = atomicAdd(&ctr[0], 1u);
+      if (i < ctr[2]) {
+        s_item = i;
+        s_mode = 0;
+      } else {  // wave-sized segments: one per wave
+        s_item = atomicAdd(&ctr[3], static_cast<uint32_t>(kWaves));
+        s_mode = 1;
+      }
+    }
     __syncthreads();
     const uint32_t item = s_item;
+    if (s_mode == 1) {
+      if (item >= ctr[1]) return;
+      const uint32_t mine = item + tid / kWave;
+      if (mine < ctr[1]) {
+        uint64_t begin;
+        const uint64_t len = seg_len(off, worklist[mine], n_total, &begin);
+        const int valid = static_cast<int>(len);  // 1 .. kTinyKeys - 1
+        const uint32_t lane = lane_id();
+        const int wave = tid / kWave;
+        K* wk = s_stage + wave * padded16(kTinyKeys);
+        uint32_t* wv = s_vstage + (VALS ? wave * padded16(kTinyKeys) : 0);
+        uint32_t* wc = reinterpret_cast<uint32_t*>(wk);
+#pragma unroll
+        for (int j = 0; j < kKpt; ++j) {
+          const int idx = static_cast<int>(lane) * kKpt + j;
+          keys[j] = idx < valid ? flip_key(kin[begin + idx], flip) : ~K(0);
+          if constexpr (VALS) vals[j] = idx < valid ? vin[begin + idx] : 0u;
+        }
+        // bits in which the wave's real keys differ (wave-wide OR)
+        const K k0 = flip_key(kin[begin], flip);
+        K d = 0;
+#pragma unroll
+        for (int j = 0; j < kKpt; ++j)
+          if (static_cast<int>(lane) * kKpt + j < valid) d |= keys[j] ^ k0;
+        uint64_t diff = static_cast<uint64_t>(d);
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) diff |= __shfl_xor(diff, o, kWave);
+        for (int p = 0; p < P; ++p) {
+          if (((diff >> (8 * p)) & (kRadix - 1)) == 0) continue;  // uniform across the wave
+          wave_sort_digit<kKpt, VALS>(keys, vals, 8 * p, wk, wv, wc);
+        }
+#pragma unroll
+        for (int j = 0; j < kKpt; ++j) {
+          const int idx = static_cast<int>(lane) * kKpt + j;
+          if (idx < valid) {
+            kout[begin + idx] = flip_key(keys[j], flip);
+            if constexpr (VALS) vout[begin + idx] = vals[j];
+          }
+        }
+      }
+      continue;
+    }
     if (item >= ctr[1]) return;
     uint64_t begin;
     const uint64_t len = seg_len(off, worklist[item], n_total, &begin);

@@ -129,7 +129,7 @@ int main(int argc, char** argv) {
     run_sort<uint32_t>(MS_KEY_I32, 12000, "sorted", false, true, 512);
     run_sort<uint64_t>(MS_KEY_U64, 9000, "few", true, false, 256);
     run_sort<uint32_t>(MS_KEY_I32, 300, "uniform", true, false, 256);
-    run_segmented<uint32_t>(MS_KEY_I32, {0, 5, 9000, 1, 300}, true);
+    run_segmented<uint32_t>(MS_KEY_I32, {0, 5, 9000, 1, 300, 1000, 64, 2, 900, 17, 18, 19, 20}, true);
     run_merge<uint32_t>(MS_KEY_U32, {3000, 0, 2500, 1});
   }
   if (what == "all" || what == "sort") {
@@ -153,6 +153,8 @@ int main(int argc, char** argv) {
   if (what == "all" || what == "segmented" || what == "seg") {
     run_segmented<uint32_t>(MS_KEY_I32, {0, 5, 9000, 1, 0, 8192, 8193, 300}, false);
     run_segmented<uint32_t>(MS_KEY_I32, {20000, 17, 16, 4000, 0, 1}, true);
+    run_segmented<uint32_t>(MS_KEY_I32, {5, 1023, 1024, 700, 64, 65, 1, 2, 1000, 900, 3, 800}, true);
+    run_segmented<uint64_t>(MS_KEY_U64, {5, 1023, 1024, 700, 9000, 65, 1, 2, 1000, 900, 3, 800}, false);
     run_segmented<uint32_t>(MS_KEY_U32, {7000, 10000, 3}, true);
     run_segmented<uint64_t>(MS_KEY_U64, {5000, 4096, 4097, 0}, true);
   }

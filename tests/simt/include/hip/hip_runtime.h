@@ -100,6 +100,7 @@ inline uint32_t __builtin_amdgcn_mbcnt_hi(uint32_t m, uint32_t acc) {
 inline uint32_t __builtin_amdgcn_readfirstlane(uint32_t v) { return static_cast<uint32_t>(simt::shfl_u64(v, 0)); }
 inline void __builtin_amdgcn_s_sleep(int) { simt::yield(); }
 inline void __builtin_amdgcn_wave_barrier() { simt::wave_sync(); }
+inline void __builtin_amdgcn_fence(int, const char*) {}
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 inline int __popc(unsigned x) { return __builtin_popcount(x); }
 
@@ -108,6 +109,18 @@ inline T __shfl_up(T v, unsigned delta, int width = 64) {
   (void)width;
   const uint32_t l = simt::lane();
   const int src = l >= delta ? static_cast<int>(l - delta) : static_cast<int>(l);
+  uint64_t bits = 0;
+  memcpy(&bits, &v, sizeof(T));
+  const uint64_t got = simt::shfl_u64(bits, src);
+  T out;
+  memcpy(&out, &got, sizeof(T));
+  return out;
+}
+
+template <typename T>
+inline T __shfl_xor(T v, int mask, int width = 64) {
+  (void)width;
+  const int src = static_cast<int>(simt::lane()) ^ mask;
   uint64_t bits = 0;
   memcpy(&bits, &v, sizeof(T));
   const uint64_t got = simt::shfl_u64(bits, src);
