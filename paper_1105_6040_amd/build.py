@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -40,16 +41,40 @@ def sources():
     return out
 
 
+RESOURCE_REMARKS = "-Rpass-analysis=kernel-resource-usage"
+
+
+def spilling_kernels(remarks: str):
+    """(kernel, bytes per lane) for every kernel whose resource-usage remark
+    reports private scratch: register spills, which these kernels must not
+    have (a spilled tile kernel loses its occupancy and its speed)."""
+    out, name = [], None
+    for ln in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", ln)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", ln)
+        if m and int(m.group(1)) > 0:
+            out.append((name, int(m.group(1))))
+    return out
+
+
 def _compile(src: str, extra) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *COMMON, *extra, *lang, "-c", src, "-o", obj]
+    remarks = [RESOURCE_REMARKS] if src.endswith(".hip") else []
+    cmd = [HIPCC, *COMMON, *extra, *lang, *remarks, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    spills = spilling_kernels(r.stderr)
+    if spills:
+        raise RuntimeError(f"{src}: kernels spill registers to scratch: {spills}")
     if r.stderr.strip():
         # warnings other than the host pass not knowing the packed-fp32 feature
-        lines = [ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
+        lines = [ln for ln in r.stderr.splitlines()
+                 if "packed-fp32-ops" not in ln and "kernel-resource-usage" not in ln and ln.strip()]
         if lines:
             sys.stderr.write("\n".join(lines) + "\n")
     return obj

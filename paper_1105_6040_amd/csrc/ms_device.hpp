@@ -14,6 +14,36 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
 // ---------------------------------------------------------------------------
+// Global-memory view of a pointer the compiler cannot place by itself (one
+// read from device memory rather than passed as a kernel argument).  Accesses
+// through a generic pointer become FLAT instructions, which also count
+// against the LDS wait counter: every later LDS access of the wave would then
+// wait for them to finish.  Address spaces exist in device code only; the
+// host pass (which parses device functions too) sees a plain pointer.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <typename T>
+using gptr = T*;
+#endif
+
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)(p);
+}
+
+// Returns a wave-uniform value unchanged, hiding from the compiler that it is
+// the same value, so that expressions computed from it are evaluated again
+// instead of being kept in registers from an earlier evaluation.
+__device__ __forceinline__ int opaque_uniform(int x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+s"(x));
+#endif
+  return x;
+}
+
+// ---------------------------------------------------------------------------
 // Key codec.  Radix passes work on unsigned bit patterns; a signed int32 key
 // becomes order-preserving unsigned by flipping bit 31 (`flip` = 0x80000000),
 // unsigned keys pass through (`flip` = 0).  The map is its own inverse.
@@ -50,16 +80,42 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d) {
   return m;
 }
 
-// Inclusive prefix sum across the 64 lanes of a wave.
+// DPP controls (GFX9 encoding) used by the wave scan.
+constexpr int kDppRowShr = 0x110;     // + n: lane reads lane - n of its row of 16
+constexpr int kDppRowBcast15 = 0x142;  // lane 15 of each row to the next row
+constexpr int kDppRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
+
+template <int kCtrl, int kRowMask, bool kBoundZero>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(v), kCtrl, kRowMask, 0xf, kBoundZero));
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.  32-bit values use
+// DPP lane moves (no LDS traffic): scans of shift 1, 2, 4, 8 within each row
+// of 16 lanes, then the total of row 0 is added to row 1 and of row 2 to
+// row 3 (row_bcast:15), then the total of rows 0-1 to rows 2-3
+// (row_bcast:31).  Lanes a move does not reach receive 0.
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T v) {
-  const uint32_t lane = lane_id();
+  if constexpr (sizeof(T) == 4) {
+    uint32_t x = static_cast<uint32_t>(v);
+    x += dpp_u32<kDppRowShr + 1, 0xf, true>(x);
+    x += dpp_u32<kDppRowShr + 2, 0xf, true>(x);
+    x += dpp_u32<kDppRowShr + 4, 0xf, true>(x);
+    x += dpp_u32<kDppRowShr + 8, 0xf, true>(x);
+    x += dpp_u32<kDppRowBcast15, 0xa, false>(x);
+    x += dpp_u32<kDppRowBcast31, 0xc, false>(x);
+    return static_cast<T>(x);
+  } else {
+    const uint32_t lane = lane_id();
 #pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const T u = __shfl_up(v, off, kWave);
-    if (lane >= static_cast<uint32_t>(off)) v += u;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const T u = __shfl_up(v, off, kWave);
+      if (lane >= static_cast<uint32_t>(off)) v += u;
+    }
+    return v;
   }
-  return v;
 }
 
 // Exclusive prefix sum over the first kRadix threads of a block of THREADS
@@ -167,16 +223,16 @@ __device__ __forceinline__ uint32_t tile_digit_starts(uint32_t (*whist)[kRadix],
 
 // Decoupled look-back over the status rows of earlier tiles for one digit:
 // `st` points at this tile's word for the digit, rows are `stride` words
-// apart.  Reads kWindow predecessors at once (independent loads in flight),
-// adds AGGREGATE counts nearest-first until an INCLUSIVE count ends the walk,
-// and waits on a predecessor that has published nothing yet.  Tile 0
-// publishes INCLUSIVE directly, so the walk always ends.  Returns the
-// exclusive prefix of the digit over all earlier tiles.
+// apart.  Starting at predecessor tile p and walking towards tile 0, reads
+// kWindow predecessors at once (independent loads in flight), adds AGGREGATE
+// counts nearest-first until an INCLUSIVE count ends the walk, and waits on a
+// predecessor that has published nothing yet.  Tile 0 publishes INCLUSIVE
+// directly, so the walk always ends.  Returns the count of the digit in tiles
+// 0..p.
 template <typename C, typename S, int kWindow = 8>
-__device__ __forceinline__ C lookback(const S* st, uint32_t tile, size_t stride) {
+__device__ __forceinline__ C lookback_from(const S* st, uint32_t tile, int64_t p, size_t stride) {
   using St = Status<S>;
   C excl = 0;
-  int64_t p = static_cast<int64_t>(tile) - 1;
   while (true) {
     S w[kWindow];
 #pragma unroll
@@ -197,6 +253,120 @@ __device__ __forceinline__ C lookback(const S* st, uint32_t tile, size_t stride)
     if (done) return excl;
     p -= used;
     if (used == 0) __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// The exclusive prefix of the digit over all tiles before `tile`.
+template <typename C, typename S, int kWindow = 8>
+__device__ __forceinline__ C lookback(const S* st, uint32_t tile, size_t stride) {
+  return lookback_from<C, S, kWindow>(st, tile, static_cast<int64_t>(tile) - 1, stride);
+}
+
+// Look-back agent: one workgroup of a pass that takes no tile but walks the
+// status rows in tile order, and as soon as a tile's AGGREGATE word of a digit
+// is visible publishes that tile's INCLUSIVE count, so that a tile usually
+// finds its predecessor INCLUSIVE when it needs it instead of walking back
+// itself.  It only reads words the tiles publish unconditionally (AGGREGATE or
+// INCLUSIVE) and tiles never wait for it, so it adds no dependence a tile
+// could block on.  An INCLUSIVE word already published (tile 0, or a tile
+// that walked back by itself) restarts the running count at its value.
+//
+// Thread t follows digit t % kRadix over the kW tiles of chunk t / kRadix of
+// the current window, so THREADS / kRadix chunks read THREADS / kRadix * kW
+// rows per memory round trip.  `val` and `used` hold THREADS entries,
+// `prefix` and `next` kRadix.  Contains barriers; every thread of the block
+// calls it.  Returns when every tile of every digit has been published.
+constexpr uint32_t kLbIncBit = 1u << 16;
+
+template <int THREADS, typename C, typename S>
+__device__ __forceinline__ void lookback_agent(S* status, uint32_t num_tiles, C* val, uint32_t* used, C* prefix,
+                                               uint32_t* next) {
+  using St = Status<S>;
+  constexpr int kChunks = THREADS / kRadix;
+  constexpr int kW = 16;
+  static_assert(THREADS % kRadix == 0, "whole chunks of digits");
+  const int tid = threadIdx.x;
+  const int d = tid % kRadix;
+  const int c = tid / kRadix;
+  if (tid < kRadix) {
+    next[tid] = 0;
+    prefix[tid] = 0;
+  }
+  __syncthreads();
+  while (true) {
+    const uint32_t start = next[d];
+    if (!__syncthreads_or(tid < kRadix && start < num_tiles)) break;
+    // Read the chunk and fold it: u = words ready (published) from its start,
+    // running = its effect on the count (set by an INCLUSIVE word, else added).
+    const uint32_t base = start + static_cast<uint32_t>(c) * kW;
+    S w[kW];
+#pragma unroll
+    for (int i = 0; i < kW; ++i)
+      w[i] = base + i < num_tiles ? status_load(status + static_cast<size_t>(base + i) * kRadix + d) : S(0);
+    uint32_t u = 0;
+    bool stop = false, has_inc = false;
+    C run = 0;
+#pragma unroll
+    for (int i = 0; i < kW; ++i) {
+      const S flag = w[i] & St::kFlagMask;
+      const bool ready = !stop && flag != 0;
+      stop = !ready;
+      u += ready ? 1u : 0u;
+      const C v = static_cast<C>(w[i] & St::kValMask);
+      if (ready && flag == St::kInc) {
+        has_inc = true;
+        run = v;
+      } else if (ready) {
+        run += v;
+      }
+    }
+    val[tid] = run;
+    used[tid] = u | (has_inc ? kLbIncBit : 0u);
+    __syncthreads();
+    // Count entering this chunk: the chunks before it, while each was ready
+    // to its end.  Publish INCLUSIVE for the chunk's ready AGGREGATE words.
+    C pin = prefix[d];
+    bool reach = true;
+#pragma unroll
+    for (int k = 0; k < kChunks - 1; ++k) {
+      if (k < c && reach) {
+        const uint32_t uk = used[k * kRadix + d];
+        const C vk = val[k * kRadix + d];
+        pin = (uk & kLbIncBit) ? vk : pin + vk;
+        reach = (uk & ~kLbIncBit) == static_cast<uint32_t>(kW);
+      }
+    }
+    if (reach) {
+      C incl = pin;
+#pragma unroll
+      for (int i = 0; i < kW; ++i) {
+        if (static_cast<uint32_t>(i) < u) {
+          const S flag = w[i] & St::kFlagMask;
+          const C v = static_cast<C>(w[i] & St::kValMask);
+          incl = flag == St::kInc ? v : incl + v;
+          if (flag == St::kAgg) status_store(status + static_cast<size_t>(base + i) * kRadix + d, St::kInc | static_cast<S>(incl));
+        }
+      }
+    }
+    if (tid < kRadix) {
+      C p = prefix[d];
+      uint32_t adv = 0;
+      bool go = true;
+#pragma unroll
+      for (int k = 0; k < kChunks; ++k) {
+        if (go) {
+          const uint32_t uk = used[k * kRadix + d];
+          const C vk = val[k * kRadix + d];
+          p = (uk & kLbIncBit) ? vk : p + vk;
+          adv += uk & ~kLbIncBit;
+          go = (uk & ~kLbIncBit) == static_cast<uint32_t>(kW);
+        }
+      }
+      next[d] = start + adv;
+      prefix[d] = p;
+      if (adv == 0) __builtin_amdgcn_s_sleep(2);
+    }
+    __syncthreads();
   }
 }
 

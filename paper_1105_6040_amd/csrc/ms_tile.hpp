@@ -62,22 +62,27 @@ template <int THREADS, int KPT, typename K>
 __device__ __forceinline__ void tile_split_positions(const K (&keys)[KPT], int shift, uint32_t (&pos)[KPT],
                                                      uint32_t* counts, uint32_t* scan) {
   static_assert(KPT <= 16, "4-bit per-thread counters hold at most 15 earlier keys");
+  static_assert(THREADS % 16 == 0, "bucket rows of whole pad16 groups");
   const int tid = threadIdx.x;
+  // Entry (bucket b, thread t) lives at pad16(b * THREADS + t), which is
+  // b * padded16(THREADS) + pad16(t) since THREADS is a multiple of 16: one
+  // base per thread plus a constant (or one multiply-add) per bucket.
+  constexpr int kRow = padded16(THREADS);
+  uint32_t* const column = counts + pad16(tid);
 
-  // 1.
+  // 1.  The last key is not counted into c (a bucket holding all KPT keys
+  // would overflow its 4-bit field); its count is added in LDS instead.
   uint64_t c = 0;
-  uint32_t bucket[KPT];
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
-    bucket[j] = static_cast<uint32_t>(keys[j] >> shift) & (kSubBuckets - 1);
-    const uint32_t sh = bucket[j] * kSubBits;
+    const uint32_t sh = (static_cast<uint32_t>(keys[j] >> shift) & (kSubBuckets - 1)) * kSubBits;
     pos[j] = static_cast<uint32_t>(c >> sh) & (kSubBuckets - 1);
     if (j + 1 < KPT) c += 1ull << sh;
   }
-  const uint32_t last = bucket[KPT - 1];
+  const uint32_t last = static_cast<uint32_t>(keys[KPT - 1] >> shift) & (kSubBuckets - 1);
 #pragma unroll
-  for (int b = 0; b < kSubBuckets; ++b)
-    counts[pad16(b * THREADS + tid)] = (static_cast<uint32_t>(c >> (b * kSubBits)) & (kSubBuckets - 1)) + (last == b);
+  for (int b = 0; b < kSubBuckets; ++b) column[b * kRow] = static_cast<uint32_t>(c >> (b * kSubBits)) & (kSubBuckets - 1);
+  atomicAdd(&column[last * kRow], 1u);  // after this thread's own store to the word (LDS keeps a wave's order)
   __syncthreads();
   uint32_t* row = counts + tid * (kSubBuckets + 1);
   uint32_t v[kSubBuckets];
@@ -94,43 +99,55 @@ __device__ __forceinline__ void tile_split_positions(const K (&keys)[KPT], int s
     run += v[i];
   }
   __syncthreads();
+  // The buckets are extracted again rather than kept from step 1: holding
+  // them through the scan would cost KPT registers at the kernel's peak.
+  const int shift_again = opaque_uniform(shift);
 #pragma unroll
-  for (int j = 0; j < KPT; ++j) pos[j] += counts[pad16(bucket[j] * THREADS + tid)];
+  for (int j = 0; j < KPT; ++j)
+    pos[j] += column[(static_cast<uint32_t>(keys[j] >> shift_again) & (kSubBuckets - 1)) * kRow];
   __syncthreads();  // callers may reuse `counts` (it can alias the key stage)
 }
 
-// Full stable reorder of a blocked tile by the 8-bit digit at `shift`, as two
-// 4-bit splits through `stage_k` (and `stage_v` for values), both indexed
-// through pad16 (padded16(THREADS * KPT) entries); `counts` may alias
-// stage_k.  On return the tile is in
-// digit order in the stage (entry pad16(i) holds the i-th key of the sorted
-// tile) and, if `reload` is set, back in registers in blocked layout.
+// One stable split of a blocked tile by bits [shift, shift+4) through
+// `stage_k` (and `stage_v` for values), both indexed through pad16
+// (padded16(THREADS * KPT) entries); `counts` may alias stage_k.  On return
+// entry pad16(i) of the stage holds the i-th key of the split tile and, if
+// `reload` is set, the tile is back in registers in blocked layout.
 // Contains barriers.
+template <int THREADS, int KPT, bool VALS, typename K>
+__device__ __forceinline__ void tile_split_stage(K (&keys)[KPT], uint32_t (&vals)[KPT], int shift, K* stage_k,
+                                                 uint32_t* stage_v, uint32_t* counts, uint32_t* scan,
+                                                 bool reload) {
+  static_assert(KPT == 16, "the blocked reload assumes 16 keys per thread");
+  const int tid = threadIdx.x;
+  uint32_t pos[KPT];
+  tile_split_positions<THREADS, KPT>(keys, shift, pos, counts, scan);
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) {
+    stage_k[pad16(pos[j])] = keys[j];
+    if constexpr (VALS) stage_v[pad16(pos[j])] = vals[j];
+  }
+  __syncthreads();
+  if (reload) {
+    // KPT == 16: pad16(tid * 16 + j) = 17 * tid + j.
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      keys[j] = stage_k[pad16(tid * KPT + j)];
+      if constexpr (VALS) vals[j] = stage_v[pad16(tid * KPT + j)];
+    }
+    __syncthreads();
+  }
+}
+
+// Full stable reorder of a blocked tile by the 8-bit digit at `shift`: the
+// split by the low nibble, then by the high nibble.  On return the tile is in
+// digit order in the stage and, if `reload` is set, back in registers in
+// blocked layout.  Contains barriers.
 template <int THREADS, int KPT, bool VALS, typename K>
 __device__ __forceinline__ void tile_sort_digit(K (&keys)[KPT], uint32_t (&vals)[KPT], int shift, K* stage_k,
                                                 uint32_t* stage_v, uint32_t* counts, uint32_t* scan, bool reload) {
-  static_assert(KPT == 16, "the blocked reload assumes 16 keys per thread");
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    uint32_t pos[KPT];
-    tile_split_positions<THREADS, KPT>(keys, shift + half * kSubBits, pos, counts, scan);
-#pragma unroll
-    for (int j = 0; j < KPT; ++j) {
-      stage_k[pad16(pos[j])] = keys[j];
-      if constexpr (VALS) stage_v[pad16(pos[j])] = vals[j];
-    }
-    __syncthreads();
-    if (half == 0 || reload) {
-      // KPT == 16: pad16(tid * 16 + j) = 17 * tid + j.
-#pragma unroll
-      for (int j = 0; j < KPT; ++j) {
-        keys[j] = stage_k[pad16(tid * KPT + j)];
-        if constexpr (VALS) vals[j] = stage_v[pad16(tid * KPT + j)];
-      }
-      __syncthreads();
-    }
-  }
+  tile_split_stage<THREADS, KPT, VALS>(keys, vals, shift, stage_k, stage_v, counts, scan, true);
+  tile_split_stage<THREADS, KPT, VALS>(keys, vals, shift + kSubBits, stage_k, stage_v, counts, scan, reload);
 }
 
 // ---------------------------------------------------------------------------

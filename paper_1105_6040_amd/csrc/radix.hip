@@ -23,6 +23,10 @@
 //                number of executed passes, or no pass executed)
 // Lists of at most one LDS tile skip all that: one workgroup sorts them in
 // LDS with every pass done on-chip.
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
 #include "ms_device.hpp"
 #include "ms_lds_sort.hpp"
 #include "ms_tile.hpp"
@@ -72,6 +76,10 @@ struct PassCfg {
   static constexpr int kThreads = THREADS;
   static constexpr int kKpt = 16;
   static constexpr int kTile = kThreads * kKpt;
+  // A look-back agent publishes prefixes for 1,024-thread tiles.  Smaller
+  // tiles arrive faster than one agent workgroup of that size can read their
+  // status rows, so those tiles walk back by themselves.
+  static constexpr bool kAgent = THREADS == 1024;
 };
 constexpr int kMinPassTile = PassCfg<256>::kTile;  // workspace is sized for the smallest tile
 
@@ -238,6 +246,64 @@ __global__ __launch_bounds__(256) void histogram_kernel(const K* __restrict__ ke
 // each digit in all earlier tiles -> publish INCLUSIVE -> write the sorted
 // tile: entry i goes to base[d] + earlier[d] + (i - start[d]), so threads
 // i, i+1, ... write consecutive addresses inside every digit run.
+//
+// Workgroups are persistent: each takes tiles in arrival order from a counter
+// until none are left.  The next tile's number is fetched while the current
+// tile is being sorted and its keys are loaded before the current tile is
+// written out, so neither round trip stands between two tiles.
+
+// Blocked load of the tile starting at `base` (raw bits: the codec is applied
+// by the caller once the loads have landed); past the end keys read as `pad`
+// and values as 0.
+template <typename K, bool VALS, typename C, int KPT>
+__device__ __forceinline__ void load_tile_keys(gptr<const K> src, gptr<const uint32_t> src_v, C my_base, C n, K pad,
+                                               K (&keys)[KPT], uint32_t (&vals)[KPT]) {
+  const bool vec_ok = (reinterpret_cast<uintptr_t>(src) % 16 == 0) && my_base + KPT <= n;
+  if (vec_ok) {
+    constexpr int kPer = 16 / sizeof(K);
+    gptr<const uint4> p4 = (gptr<const uint4>)(src + my_base);
+#pragma unroll
+    for (int q = 0; q < KPT / kPer; ++q) {
+      const uint4 v = p4[q];
+      if constexpr (sizeof(K) == 4) {
+        keys[4 * q + 0] = v.x;
+        keys[4 * q + 1] = v.y;
+        keys[4 * q + 2] = v.z;
+        keys[4 * q + 3] = v.w;
+      } else {
+        keys[2 * q + 0] = (static_cast<uint64_t>(v.y) << 32) | v.x;
+        keys[2 * q + 1] = (static_cast<uint64_t>(v.w) << 32) | v.z;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      const C idx = my_base + j;
+      keys[j] = idx < n ? src[idx] : pad;
+    }
+  }
+  if constexpr (VALS) {
+    const bool vvec = (reinterpret_cast<uintptr_t>(src_v) % 16 == 0) && my_base + KPT <= n;
+    if (vvec) {
+      gptr<const uint4> p4 = (gptr<const uint4>)(src_v + my_base);
+#pragma unroll
+      for (int q = 0; q < KPT / 4; ++q) {
+        const uint4 v = p4[q];
+        vals[4 * q + 0] = v.x;
+        vals[4 * q + 1] = v.y;
+        vals[4 * q + 2] = v.z;
+        vals[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        const C idx = my_base + j;
+        vals[j] = idx < n ? src_v[idx] : 0u;
+      }
+    }
+  }
+}
+
 template <typename K, bool VALS, typename C, typename S, int THREADS>
 __global__ __launch_bounds__(THREADS) void onesweep_kernel(
     const SortPlan* __restrict__ plan, int pass, C n, K flip, const C* __restrict__ gbase,
@@ -259,126 +325,135 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
   __shared__ C s_doff[kRadix];  // output index of the digit's first tile key, minus its tile position
   __shared__ uint32_t s_scan[kThreads / kWave];
   __shared__ C s_cscan[kRadix / kWave];
-  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_ticket;
+  // Used by the look-back agent only.
+  constexpr bool kAgent = PassCfg<THREADS>::kAgent;
+  __shared__ C s_lb_val[kAgent ? kThreads : 1];
+  __shared__ uint32_t s_lb_used[kAgent ? kThreads : 1];
 
   const int tid = threadIdx.x;
   const PassPlan& pp = plan->pass[pass];
 
+  const uint32_t num_tiles = static_cast<uint32_t>((n + kTile - 1) / kTile);
   if (!pp.active) {
-    // Skipped pass: still clear the next pass's look-back row.
+    // Skipped pass: still clear the next pass's look-back rows.
     if (status_next)
-      for (int d = tid; d < kRadix; d += kThreads) status_next[static_cast<size_t>(blockIdx.x) * kRadix + d] = 0;
+      for (uint32_t row = blockIdx.x; row < num_tiles; row += gridDim.x)
+        for (int d = tid; d < kRadix; d += kThreads) status_next[static_cast<size_t>(row) * kRadix + d] = 0;
     return;
   }
 
-  if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
-  for (int d = tid; d < kRadix; d += kThreads) s_hist[d] = 0;
+  // With an agent, the first ticket makes its workgroup the look-back agent
+  // and ticket t > 0 is tile t - 1; without, ticket t is tile t.
+  constexpr uint32_t kFirstTile = kAgent ? 1 : 0;
+  if (tid == 0) s_ticket = atomicAdd(tile_counter, 1u);
   __syncthreads();
-  const uint32_t tile = s_tile;
-  if (status_next)
-    for (int d = tid; d < kRadix; d += kThreads) status_next[static_cast<size_t>(tile) * kRadix + d] = 0;
+  if constexpr (kAgent) {
+    if (s_ticket == 0) {
+      lookback_agent<kThreads, C, S>(status_cur, num_tiles, s_lb_val, s_lb_used, s_doff, s_hist);
+      return;
+    }
+  }
+  uint32_t tile = s_ticket - kFirstTile;
+  if (tile >= num_tiles) return;
 
   const int shift = 8 * pass;
-  const C tile_base = static_cast<C>(tile) * kTile;
-  const C my_base = tile_base + static_cast<C>(tid) * kKpt;
-  const K* __restrict__ src = static_cast<const K*>(pp.src_k);
+  const gptr<const K> src = as_global(static_cast<const K*>(pp.src_k));
+  const gptr<const uint32_t> src_v = as_global(static_cast<const uint32_t*>(pp.src_v));
+  const gptr<K> dst = as_global(static_cast<K*>(pp.dst_k));
+  const gptr<uint32_t> dst_v = as_global(pp.dst_v);
   const K in_flip = pp.first ? flip : K(0);  // intermediate buffers hold encoded keys
+  const K out_flip = pp.last ? flip : K(0);
+  const K pad = ~K(0) ^ in_flip;             // decodes to all-ones: sorts after every real key
 
-  // Blocked load; past the end all-ones keys, which sort after every real key.
   K keys[kKpt];
   uint32_t vals[kKpt];  // unused (and optimised away) for key-only sorts
-  const bool vec_ok = (reinterpret_cast<uintptr_t>(src) % 16 == 0) && my_base + kKpt <= n;
-  if (vec_ok) {
-    constexpr int kPer = 16 / sizeof(K);
-    const uint4* p4 = reinterpret_cast<const uint4*>(src + my_base);
-#pragma unroll
-    for (int q = 0; q < kKpt / kPer; ++q) {
-      const uint4 v = p4[q];
-      if constexpr (sizeof(K) == 4) {
-        keys[4 * q + 0] = v.x;
-        keys[4 * q + 1] = v.y;
-        keys[4 * q + 2] = v.z;
-        keys[4 * q + 3] = v.w;
-      } else {
-        keys[2 * q + 0] = (static_cast<uint64_t>(v.y) << 32) | v.x;
-        keys[2 * q + 1] = (static_cast<uint64_t>(v.w) << 32) | v.z;
-      }
-    }
+  load_tile_keys<K, VALS, C, kKpt>(src, src_v, static_cast<C>(tile) * kTile + static_cast<C>(tid) * kKpt, n, pad,
+                                   keys, vals);
+
+  while (true) {
+    const C tile_base = static_cast<C>(tile) * kTile;
+    if (status_next)
+      for (int d = tid; d < kRadix; d += kThreads) status_next[static_cast<size_t>(tile) * kRadix + d] = 0;
+    for (int d = tid; d < kRadix; d += kThreads) s_hist[d] = 0;
 #pragma unroll
     for (int j = 0; j < kKpt; ++j) keys[j] = flip_key(keys[j], in_flip);
-  } else {
+    __syncthreads();
+
+    // Tile digit histogram.  When all keys of the wave share one digit (long
+    // runs: sorted or skewed input) one lane adds them all, sparing the LDS
+    // 64 colliding atomics per instruction; otherwise every key adds itself.
+    {
+      const uint32_t d0 = digit_of(keys[0], shift);
+      bool same = true;
 #pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      const C idx = my_base + j;
-      keys[j] = idx < n ? flip_key(src[idx], in_flip) : ~K(0);
-    }
-  }
-  if constexpr (VALS) {
-    const bool vvec = (reinterpret_cast<uintptr_t>(pp.src_v) % 16 == 0) && my_base + kKpt <= n;
-    if (vvec) {
-      const uint4* p4 = reinterpret_cast<const uint4*>(pp.src_v + my_base);
+      for (int j = 1; j < kKpt; ++j) same = same && digit_of(keys[j], shift) == d0;
+      const uint32_t w0 = __builtin_amdgcn_readfirstlane(d0);
+      if (__builtin_amdgcn_ballot_w64(same && d0 == w0) == ~0ull) {
+        if (lane_id() == 0) atomicAdd(&s_hist[w0], static_cast<uint32_t>(kWave * kKpt));
+      } else {
 #pragma unroll
-      for (int q = 0; q < kKpt / 4; ++q) {
-        const uint4 v = p4[q];
-        vals[4 * q + 0] = v.x;
-        vals[4 * q + 1] = v.y;
-        vals[4 * q + 2] = v.z;
-        vals[4 * q + 3] = v.w;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        const C idx = my_base + j;
-        vals[j] = idx < n ? pp.src_v[idx] : 0u;
+        for (int j = 0; j < kKpt; ++j) atomicAdd(&s_hist[digit_of(keys[j], shift)], 1u);
       }
     }
-  }
+    __syncthreads();
 
-  // Tile digit histogram.
-#pragma unroll
-  for (int j = 0; j < kKpt; ++j) {
-    const uint32_t d = digit_of(keys[j], shift);
-    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-    if (__builtin_amdgcn_ballot_w64(d == d0) == ~0ull) {
-      if (lane_id() == 0) atomicAdd(&s_hist[d0], static_cast<uint32_t>(kWave));
-    } else {
-      atomicAdd(&s_hist[d], 1u);
+    // Publish this tile's digit counts before sorting it.
+    S* st = status_cur + static_cast<size_t>(tile) * kRadix + tid;
+    uint32_t cnt = 0;
+    if (tid < kRadix) {
+      cnt = s_hist[tid];
+      status_store(st, (tile == 0 ? St::kInc : St::kAgg) | static_cast<S>(cnt));
     }
-  }
-  __syncthreads();
 
-  // Publish this tile's digit counts before sorting it.
-  S* st = status_cur + static_cast<size_t>(tile) * kRadix + tid;
-  uint32_t cnt = 0;
-  if (tid < kRadix) {
-    cnt = s_hist[tid];
-    status_store(st, (tile == 0 ? St::kInc : St::kAgg) | static_cast<S>(cnt));
-  }
+    // Sort the tile by the digit's low nibble.
+    tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift, s_stage, s_vstage, s_counts, s_scan, true);
 
-  tile_sort_digit<kThreads, kKpt, VALS>(keys, vals, shift, s_stage, s_vstage, s_counts, s_scan, false);
+    // Fetch the next ticket, and read the predecessor's word, while the
+    // second split runs: by the time the word is used the agent has usually
+    // published the predecessor's INCLUSIVE count.
+    uint32_t ticket = 0;
+    if (tid == 0) ticket = atomicAdd(tile_counter, 1u);
+    S pred = 0;
+    if (tid < kRadix && tile != 0) pred = status_load(st - kRadix);
 
-  C tile_total;
-  const C start = block_exclusive_scan_radix<kThreads>(static_cast<C>(cnt), s_cscan, &tile_total);
-  if (tid < kRadix) {
-    C excl = 0;
-    if (tile != 0) {
-      excl = lookback<C, S, 16>(st, tile, kRadix);
-      status_store(st, St::kInc | static_cast<S>(excl + cnt));
+    // ... and by the high nibble: the stage now holds the tile in digit order.
+    tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift + kSubBits, s_stage, s_vstage, s_counts, s_scan, false);
+
+    if (tid == 0) s_ticket = ticket;
+    C tile_total;
+    const C start = block_exclusive_scan_radix<kThreads>(static_cast<C>(cnt), s_cscan, &tile_total);
+    if (tid < kRadix) {
+      C excl = 0;
+      if (tile != 0) {
+        // Otherwise walk back (the agent may be behind, or there is none).
+        excl = (pred & St::kFlagMask) == St::kInc ? static_cast<C>(pred & St::kValMask)
+                                                  : lookback<C, S, 16>(st, tile, kRadix);
+        status_store(st, St::kInc | static_cast<S>(excl + cnt));
+      }
+      s_doff[tid] = gbase[tid] + excl - start;
     }
-    s_doff[tid] = gbase[tid] + excl - start;
-  }
-  __syncthreads();
+    __syncthreads();
 
-  const C remaining = n - tile_base;
-  const int valid = remaining < static_cast<C>(kTile) ? static_cast<int>(remaining) : kTile;
-  K* __restrict__ dst = static_cast<K*>(pp.dst_k);
-  const K out_flip = pp.last ? flip : K(0);
+    // Start loading the next tile, then write this one out.
+    const uint32_t next = s_ticket - kFirstTile;
+    const bool more = next < num_tiles;
+    if (more)
+      load_tile_keys<K, VALS, C, kKpt>(src, src_v, static_cast<C>(next) * kTile + static_cast<C>(tid) * kKpt, n,
+                                       pad, keys, vals);
+
+    const C remaining = n - tile_base;
+    const int valid = remaining < static_cast<C>(kTile) ? static_cast<int>(remaining) : kTile;
 #pragma unroll 4
-  for (int i = tid; i < valid; i += kThreads) {
-    const K k = s_stage[pad16(i)];
-    const C o = s_doff[digit_of(k, shift)] + static_cast<C>(i);
-    dst[o] = k ^ out_flip;
-    if constexpr (VALS) pp.dst_v[o] = s_vstage[pad16(i)];
+    for (int i = tid; i < valid; i += kThreads) {
+      const K k = s_stage[pad16(i)];
+      const C o = s_doff[digit_of(k, shift)] + static_cast<C>(i);
+      dst[o] = k ^ out_flip;
+      if constexpr (VALS) dst_v[o] = s_vstage[pad16(i)];
+    }
+    if (!more) break;
+    tile = next;
+    __syncthreads();  // the stage, s_doff and s_hist are reused by the next tile
   }
 }
 
@@ -387,12 +462,14 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
 template <typename K, bool VALS>
 __global__ __launch_bounds__(256) void plan_copy_kernel(const SortPlan* __restrict__ plan, uint64_t n) {
   if (!plan->copy) return;
-  const K* __restrict__ sk = static_cast<const K*>(plan->copy_src_k);
-  K* __restrict__ dk = static_cast<K*>(plan->copy_dst_k);
+  const gptr<const K> sk = as_global(static_cast<const K*>(plan->copy_src_k));
+  const gptr<K> dk = as_global(static_cast<K*>(plan->copy_dst_k));
+  const gptr<const uint32_t> sv = as_global(plan->copy_src_v);
+  const gptr<uint32_t> dv = as_global(plan->copy_dst_v);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
     dk[i] = sk[i];
-    if constexpr (VALS) plan->copy_dst_v[i] = plan->copy_src_v[i];
+    if constexpr (VALS) dv[i] = sv[i];
   }
 }
 
@@ -451,11 +528,47 @@ ms_status run_small(const void* kin, const uint32_t* vin, void* kout, uint32_t* 
   return MS_OK;
 }
 
+// Workgroups of `kernel` the current device holds at once (`fallback` when
+// the runtime cannot say), remembered per kernel and device.
+uint64_t resident_blocks(const void* kernel, int threads, uint64_t fallback) {
+  struct Entry {
+    const void* kernel;
+    int device;
+    uint64_t blocks;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fallback;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry& e : cache)
+      if (e.kernel == kernel && e.device == dev) return e.blocks;
+  }
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu <= 0 ||
+      cus <= 0) {
+    (void)hipGetLastError();
+    return fallback;
+  }
+  const uint64_t blocks = static_cast<uint64_t>(per_cu) * static_cast<uint64_t>(cus);
+  std::lock_guard<std::mutex> lock(mu);
+  cache.push_back({kernel, dev, blocks});
+  return blocks;
+}
+
 template <typename K, bool VALS, typename C, typename S, int THREADS>
 ms_status launch_pass_t(uint64_t n, SortPlan* plan, int p, K flip, const C* gbase, uint32_t* ctr, S* cur, S* next,
                         hipStream_t s) {
   const uint64_t tiles = (n + PassCfg<THREADS>::kTile - 1) / PassCfg<THREADS>::kTile;
-  MS_LAUNCH("onesweep_pass", (onesweep_kernel<K, VALS, C, S, THREADS>), static_cast<uint32_t>(tiles), THREADS, s,
+  // Persistent workgroups: as many as fit on the device at once (never more
+  // than tiles), plus the look-back agent where there is one.
+  const uint64_t blocks =
+      std::min<uint64_t>(tiles, resident_blocks(reinterpret_cast<const void*>(&onesweep_kernel<K, VALS, C, S, THREADS>),
+                                                THREADS, tiles)) +
+      (PassCfg<THREADS>::kAgent ? 1 : 0);
+  MS_LAUNCH("onesweep_pass", (onesweep_kernel<K, VALS, C, S, THREADS>), static_cast<uint32_t>(blocks), THREADS, s,
             static_cast<const SortPlan*>(plan), p, static_cast<C>(n), flip, gbase, ctr, cur, next);
   return MS_OK;
 }
@@ -469,12 +582,13 @@ constexpr int pass_lds_bytes() {
   return (stage > counts ? stage : counts) + (VALS ? padded16(PassCfg<THREADS>::kTile) * 4 : 0) + 4096;
 }
 
-// 1,024-thread tiles are used for 32-bit keys without values only: the other
-// forms need more than the 128 VGPRs a 1,024-thread workgroup may hold and
-// would run with register spills, so they take 512-thread tiles.
-template <typename K, bool VALS>
+// 1,024-thread tiles are used for 32-bit keys without values, counted in
+// 32-bit words (lists below 2^30 keys), only: the other forms need more than
+// the 128 VGPRs a 1,024-thread workgroup may hold and would run with register
+// spills, so they take 512-thread tiles.
+template <typename K, bool VALS, typename S>
 constexpr bool pass_1024_ok() {
-  return sizeof(K) == 4 && !VALS && pass_lds_bytes<K, VALS, 1024>() <= 160 * 1024;
+  return sizeof(K) == 4 && !VALS && sizeof(S) == 4 && pass_lds_bytes<K, VALS, 1024>() <= 160 * 1024;
 }
 
 template <typename K, bool VALS, typename C, typename S>
@@ -482,7 +596,7 @@ ms_status launch_pass(int threads, uint64_t n, SortPlan* plan, int p, K flip, co
                       S* next, hipStream_t s) {
   switch (threads) {
     case 1024:
-      if constexpr (pass_1024_ok<K, VALS>())
+      if constexpr (pass_1024_ok<K, VALS, S>())
         return launch_pass_t<K, VALS, C, S, 1024>(n, plan, p, flip, gbase, ctr, cur, next, s);
       else
         return launch_pass_t<K, VALS, C, S, 512>(n, plan, p, flip, gbase, ctr, cur, next, s);

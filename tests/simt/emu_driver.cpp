@@ -129,6 +129,9 @@ int main(int argc, char** argv) {
     run_sort<uint32_t>(MS_KEY_I32, 12000, "sorted", false, true, 512);
     run_sort<uint64_t>(MS_KEY_U64, 9000, "few", true, false, 256);
     run_sort<uint32_t>(MS_KEY_I32, 300, "uniform", true, false, 256);
+    // 1,024-thread tiles: look-back agent, persistent workgroups over several tiles each
+    run_sort<uint32_t>(MS_KEY_I32, 120000, "uniform", false, false, 1024);
+    run_sort<uint32_t>(MS_KEY_U32, 70001, "small", false, true, 1024);
     run_segmented<uint32_t>(MS_KEY_I32, {0, 5, 9000, 1, 300, 1000, 64, 2, 900, 17, 18, 19, 20}, true);
     run_merge<uint32_t>(MS_KEY_U32, {3000, 0, 2500, 1});
   }

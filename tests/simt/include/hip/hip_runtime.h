@@ -11,6 +11,8 @@
 #pragma once
 
 #include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <stddef.h>
 #include <string.h>
 
@@ -55,6 +57,22 @@ inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) {
   return hipSuccess;
 }
 inline hipError_t hipEventDestroy(hipEvent_t) { return hipSuccess; }
+// The emulated device: one device of kSimtCUs compute units holding one
+// workgroup each, so persistent kernels loop over many tiles per workgroup.
+constexpr int kSimtCUs = 2;
+typedef enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount = 1 } hipDeviceAttribute_t;
+inline hipError_t hipGetDevice(int* d) {
+  *d = 0;
+  return hipSuccess;
+}
+inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int) {
+  *v = a == hipDeviceAttributeMultiprocessorCount ? kSimtCUs : 0;
+  return hipSuccess;
+}
+inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void*, int, size_t) {
+  *n = 1;
+  return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // Emulator core (tests/simt/simt.cpp).
@@ -100,6 +118,34 @@ inline uint32_t __builtin_amdgcn_mbcnt_hi(uint32_t m, uint32_t acc) {
 inline uint32_t __builtin_amdgcn_readfirstlane(uint32_t v) { return static_cast<uint32_t>(simt::shfl_u64(v, 0)); }
 inline void __builtin_amdgcn_s_sleep(int) { simt::yield(); }
 inline void __builtin_amdgcn_wave_barrier() { simt::wave_sync(); }
+// DPP move (GFX9 rules) for the controls the kernels use: row_shr:1..15
+// (0x111..0x11f, within rows of 16 lanes) and row_bcast:15 / row_bcast:31
+// (0x142 / 0x143).  Lanes of rows disabled by row_mask keep `old`; lanes
+// whose source lies outside the row read 0 with bound_ctrl, else keep `old`.
+inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+  const int l = static_cast<int>(simt::lane());
+  const int row = l / 16, r = l % 16;
+  int from = -1;
+  if (ctrl >= 0x111 && ctrl <= 0x11f) {
+    const int n = ctrl - 0x110;
+    from = r >= n ? l - n : -1;
+  } else if (ctrl == 0x142) {
+    from = row >= 1 ? row * 16 - 1 : -1;
+  } else if (ctrl == 0x143) {
+    from = row >= 2 ? 31 : -1;
+  } else {
+    fprintf(stderr, "simt: unsupported dpp control 0x%x\n", ctrl);
+    abort();
+  }
+  if (bank_mask != 0xf) {
+    fprintf(stderr, "simt: unsupported dpp bank mask 0x%x\n", bank_mask);
+    abort();
+  }
+  const uint64_t got = simt::shfl_u64(static_cast<uint32_t>(src), from >= 0 ? from : l);
+  if (!((row_mask >> row) & 1)) return old;
+  if (from < 0) return bound_ctrl ? 0 : old;
+  return static_cast<int>(static_cast<uint32_t>(got));
+}
 inline void __builtin_amdgcn_fence(int, const char*) {}
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 inline int __popc(unsigned x) { return __builtin_popcount(x); }
