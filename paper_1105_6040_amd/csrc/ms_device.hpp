@@ -33,6 +33,30 @@ __device__ __forceinline__ gptr<T> as_global(T* p) {
   return (gptr<T>)(p);
 }
 
+// LDS view of a shared-memory pointer, for the builtins that need one.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using lptr = __attribute__((address_space(3))) T*;
+#else
+template <typename T>
+using lptr = T*;
+#endif
+
+// Workgroup barrier that orders LDS accesses only: it waits for the wave's
+// own LDS operations, then meets the other waves.  Unlike __syncthreads it
+// does not wait for global memory operations in flight, among them loads
+// that land in LDS (which a plain barrier must treat as LDS writes): code
+// using it must not pass data through global memory between threads of the
+// workgroup, and reads LDS filled by such loads only in the wave that issued
+// them, after waiting for them.
+__device__ __forceinline__ void lds_barrier() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+#else
+  __syncthreads();
+#endif
+}
+
 // Returns a wave-uniform value unchanged, hiding from the compiler that it is
 // the same value, so that expressions computed from it are evaluated again
 // instead of being kept in registers from an earlier evaluation.
@@ -129,7 +153,7 @@ __device__ __forceinline__ T block_exclusive_scan_radix(T v, T* scratch, T* tota
   const int wave = tid / kWave;
   const T incl = wave_inclusive_scan(tid < kRadix ? v : T(0));
   if (tid < kRadix && (tid % kWave) == kWave - 1) scratch[wave] = incl;
-  __syncthreads();
+  lds_barrier();
   T base = 0, sum = 0;
 #pragma unroll
   for (int w = 0; w < kRadix / kWave; ++w) {
@@ -137,7 +161,7 @@ __device__ __forceinline__ T block_exclusive_scan_radix(T v, T* scratch, T* tota
     if (w < wave) base += s;
     sum += s;
   }
-  __syncthreads();
+  lds_barrier();
   *total = sum;
   return tid < kRadix ? base + incl - v : T(0);
 }
@@ -262,7 +286,7 @@ __device__ __forceinline__ C lookback(const S* st, uint32_t tile, size_t stride)
   return lookback_from<C, S, kWindow>(st, tile, static_cast<int64_t>(tile) - 1, stride);
 }
 
-// Look-back agent: one workgroup of a pass that takes no tile but walks the
+// Look-back agent: a workgroup of a pass that takes no tile but walks the
 // status rows in tile order, and as soon as a tile's AGGREGATE word of a digit
 // is visible publishes that tile's INCLUSIVE count, so that a tile usually
 // finds its predecessor INCLUSIVE when it needs it instead of walking back
@@ -271,38 +295,40 @@ __device__ __forceinline__ C lookback(const S* st, uint32_t tile, size_t stride)
 // could block on.  An INCLUSIVE word already published (tile 0, or a tile
 // that walked back by itself) restarts the running count at its value.
 //
-// Thread t follows digit t % kRadix over the kW tiles of chunk t / kRadix of
-// the current window, so THREADS / kRadix chunks read THREADS / kRadix * kW
-// rows per memory round trip.  `val` and `used` hold THREADS entries,
-// `prefix` and `next` kRadix.  Contains barriers; every thread of the block
-// calls it.  Returns when every tile of every digit has been published.
+// One agent serves kDigits digits starting at digit0 (several agents share
+// the radix, so that no single workgroup has to move all the status words).
+// Thread t follows digit digit0 + t % kDigits over the kW tiles of chunk
+// t / kDigits of the current window: THREADS / kDigits * kW rows per memory
+// round trip.  `val` and `used` hold THREADS entries, `prefix` and `next`
+// kDigits.  Contains barriers; every thread of the block calls it.  Returns
+// when every tile of its digits has been published.
 constexpr uint32_t kLbIncBit = 1u << 16;
 
-template <int THREADS, typename C, typename S>
-__device__ __forceinline__ void lookback_agent(S* status, uint32_t num_tiles, C* val, uint32_t* used, C* prefix,
-                                               uint32_t* next) {
+template <int THREADS, int kDigits, int kW, typename C, typename S>
+__device__ __forceinline__ void lookback_agent(S* status, uint32_t num_tiles, int digit0, C* val, uint32_t* used,
+                                               C* prefix, uint32_t* next) {
   using St = Status<S>;
-  constexpr int kChunks = THREADS / kRadix;
-  constexpr int kW = 16;
-  static_assert(THREADS % kRadix == 0, "whole chunks of digits");
+  constexpr int kChunks = THREADS / kDigits;
+  static_assert(THREADS % kDigits == 0 && kRadix % kDigits == 0, "whole chunks of digits");
   const int tid = threadIdx.x;
-  const int d = tid % kRadix;
-  const int c = tid / kRadix;
-  if (tid < kRadix) {
+  const int d = tid % kDigits;
+  const int c = tid / kDigits;
+  S* const column = status + digit0 + d;
+  if (tid < kDigits) {
     next[tid] = 0;
     prefix[tid] = 0;
   }
   __syncthreads();
   while (true) {
     const uint32_t start = next[d];
-    if (!__syncthreads_or(tid < kRadix && start < num_tiles)) break;
+    if (!__syncthreads_or(tid < kDigits && start < num_tiles)) break;
     // Read the chunk and fold it: u = words ready (published) from its start,
     // running = its effect on the count (set by an INCLUSIVE word, else added).
     const uint32_t base = start + static_cast<uint32_t>(c) * kW;
     S w[kW];
 #pragma unroll
     for (int i = 0; i < kW; ++i)
-      w[i] = base + i < num_tiles ? status_load(status + static_cast<size_t>(base + i) * kRadix + d) : S(0);
+      w[i] = base + i < num_tiles ? status_load(column + static_cast<size_t>(base + i) * kRadix) : S(0);
     uint32_t u = 0;
     bool stop = false, has_inc = false;
     C run = 0;
@@ -330,8 +356,8 @@ __device__ __forceinline__ void lookback_agent(S* status, uint32_t num_tiles, C*
 #pragma unroll
     for (int k = 0; k < kChunks - 1; ++k) {
       if (k < c && reach) {
-        const uint32_t uk = used[k * kRadix + d];
-        const C vk = val[k * kRadix + d];
+        const uint32_t uk = used[k * kDigits + d];
+        const C vk = val[k * kDigits + d];
         pin = (uk & kLbIncBit) ? vk : pin + vk;
         reach = (uk & ~kLbIncBit) == static_cast<uint32_t>(kW);
       }
@@ -344,19 +370,19 @@ __device__ __forceinline__ void lookback_agent(S* status, uint32_t num_tiles, C*
           const S flag = w[i] & St::kFlagMask;
           const C v = static_cast<C>(w[i] & St::kValMask);
           incl = flag == St::kInc ? v : incl + v;
-          if (flag == St::kAgg) status_store(status + static_cast<size_t>(base + i) * kRadix + d, St::kInc | static_cast<S>(incl));
+          if (flag == St::kAgg) status_store(column + static_cast<size_t>(base + i) * kRadix, St::kInc | static_cast<S>(incl));
         }
       }
     }
-    if (tid < kRadix) {
+    if (tid < kDigits) {
       C p = prefix[d];
       uint32_t adv = 0;
       bool go = true;
 #pragma unroll
       for (int k = 0; k < kChunks; ++k) {
         if (go) {
-          const uint32_t uk = used[k * kRadix + d];
-          const C vk = val[k * kRadix + d];
+          const uint32_t uk = used[k * kDigits + d];
+          const C vk = val[k * kDigits + d];
           p = (uk & kLbIncBit) ? vk : p + vk;
           adv += uk & ~kLbIncBit;
           go = (uk & ~kLbIncBit) == static_cast<uint32_t>(kW);

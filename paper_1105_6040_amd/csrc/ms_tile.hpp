@@ -45,12 +45,12 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
   const int wave = tid / kWave;
   const uint32_t incl = wave_inclusive_scan(v);
   if ((tid % kWave) == kWave - 1) scratch[wave] = incl;
-  __syncthreads();
+  lds_barrier();
   uint32_t base = 0;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w)
     if (w < wave) base += scratch[w];
-  __syncthreads();
+  lds_barrier();
   return base + incl - v;
 }
 
@@ -83,7 +83,7 @@ __device__ __forceinline__ void tile_split_positions(const K (&keys)[KPT], int s
 #pragma unroll
   for (int b = 0; b < kSubBuckets; ++b) column[b * kRow] = static_cast<uint32_t>(c >> (b * kSubBits)) & (kSubBuckets - 1);
   atomicAdd(&column[last * kRow], 1u);  // after this thread's own store to the word (LDS keeps a wave's order)
-  __syncthreads();
+  lds_barrier();
   uint32_t* row = counts + tid * (kSubBuckets + 1);
   uint32_t v[kSubBuckets];
   uint32_t sum = 0;
@@ -98,14 +98,14 @@ __device__ __forceinline__ void tile_split_positions(const K (&keys)[KPT], int s
     row[i] = run;
     run += v[i];
   }
-  __syncthreads();
+  lds_barrier();
   // The buckets are extracted again rather than kept from step 1: holding
   // them through the scan would cost KPT registers at the kernel's peak.
   const int shift_again = opaque_uniform(shift);
 #pragma unroll
   for (int j = 0; j < KPT; ++j)
     pos[j] += column[(static_cast<uint32_t>(keys[j] >> shift_again) & (kSubBuckets - 1)) * kRow];
-  __syncthreads();  // callers may reuse `counts` (it can alias the key stage)
+  lds_barrier();  // callers may reuse `counts` (it can alias the key stage)
 }
 
 // One stable split of a blocked tile by bits [shift, shift+4) through
@@ -127,7 +127,7 @@ __device__ __forceinline__ void tile_split_stage(K (&keys)[KPT], uint32_t (&vals
     stage_k[pad16(pos[j])] = keys[j];
     if constexpr (VALS) stage_v[pad16(pos[j])] = vals[j];
   }
-  __syncthreads();
+  lds_barrier();
   if (reload) {
     // KPT == 16: pad16(tid * 16 + j) = 17 * tid + j.
 #pragma unroll
@@ -135,7 +135,7 @@ __device__ __forceinline__ void tile_split_stage(K (&keys)[KPT], uint32_t (&vals
       keys[j] = stage_k[pad16(tid * KPT + j)];
       if constexpr (VALS) vals[j] = stage_v[pad16(tid * KPT + j)];
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 

@@ -76,10 +76,13 @@ struct PassCfg {
   static constexpr int kThreads = THREADS;
   static constexpr int kKpt = 16;
   static constexpr int kTile = kThreads * kKpt;
-  // A look-back agent publishes prefixes for 1,024-thread tiles.  Smaller
-  // tiles arrive faster than one agent workgroup of that size can read their
-  // status rows, so those tiles walk back by themselves.
+  // Look-back agents publish prefixes for 1,024-thread tiles: kAgents
+  // workgroups, each serving kRadix / kAgents digits with chunks of kAgentW
+  // rows.  Smaller tiles arrive faster than agents of their size can read
+  // the status rows, so those tiles walk back by themselves.
   static constexpr bool kAgent = THREADS == 1024;
+  static constexpr int kAgents = kAgent ? 4 : 0;
+  static constexpr int kAgentW = 8;
 };
 constexpr int kMinPassTile = PassCfg<256>::kTile;  // workspace is sized for the smallest tile
 
@@ -252,6 +255,69 @@ __global__ __launch_bounds__(256) void histogram_kernel(const K* __restrict__ ke
 // tile is being sorted and its keys are loaded before the current tile is
 // written out, so neither round trip stands between two tiles.
 
+// s_waitcnt immediate (GFX9 field layout: vmcnt in bits 3:0 and 15:14,
+// expcnt 6:4, lgkmcnt 11:8) that waits until at most `vm` of the wave's vector
+// memory operations are outstanding and leaves the other counters alone.
+// Vector memory operations retire in issue order on this architecture, so it
+// waits for everything issued before the last `vm` operations.
+constexpr int waitcnt_vmcnt(int vm) { return (vm & 0xF) | ((vm >> 4) << 14) | (0x7 << 4) | (0xF << 8); }
+
+// Loads of a tile's keys straight into LDS, one 16-byte chunk per lane and
+// instruction: lane l of the wave lands at lds_dst + 16 * l (lds_dst is
+// the same for every lane).  Written in
+// assembly so that the compiler, which cannot tell which later LDS accesses
+// such a load may touch, adds no waits for it: the caller waits for it by
+// hand (read_prefetched_keys) in the issuing wave, before any exit.
+__device__ __forceinline__ void global_to_lds_x4(gptr<const void> src, uint32_t* lds_dst) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  // The destination is the same for the whole wave: make it a scalar.
+  const uint32_t lds_addr =
+      __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lptr<uint32_t>)lds_dst)));
+  // M0 carries the LDS address; the compiler's own value of M0 is kept.
+  uint32_t saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "global_load_lds_dwordx4 %2, off\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(saved)
+      : "s"(lds_addr), "v"(src)
+      : "memory");
+#else
+  __builtin_amdgcn_global_load_lds(src, lds_dst, 16, 0, 0);
+#endif
+}
+
+// Reads back this lane's four 16-byte chunks of a prefetch made by its wave
+// (chunk q at lane_src + 256 q words) after waiting until at most `kLater` of
+// the wave's vector memory operations are outstanding; the caller guarantees
+// that at least that many were issued after the prefetch.
+template <int kLater>
+__device__ __forceinline__ void read_prefetched_keys(const uint32_t* lane_src, uint32_t (&k)[16]) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uint32_t lds_addr = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lptr<const uint32_t>)lane_src));
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 a, b, c, d;
+  asm volatile(
+      "s_waitcnt vmcnt(%4)\n\t"
+      "ds_read_b128 %0, %5\n\t"
+      "ds_read_b128 %1, %5 offset:1024\n\t"
+      "ds_read_b128 %2, %5 offset:2048\n\t"
+      "ds_read_b128 %3, %5 offset:3072\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(d)
+      : "n"(kLater), "v"(lds_addr)
+      : "memory");
+  k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
+  k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
+  k[8] = c.x; k[9] = c.y; k[10] = c.z; k[11] = c.w;
+  k[12] = d.x; k[13] = d.y; k[14] = d.z; k[15] = d.w;
+#else
+  for (int q = 0; q < 4; ++q)
+    for (int e = 0; e < 4; ++e) k[4 * q + e] = lane_src[256 * q + e];
+#endif
+}
+
 // Blocked load of the tile starting at `base` (raw bits: the codec is applied
 // by the caller once the loads have landed); past the end keys read as `pad`
 // and values as 0.
@@ -326,6 +392,12 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
   __shared__ uint32_t s_scan[kThreads / kWave];
   __shared__ C s_cscan[kRadix / kWave];
   __shared__ uint32_t s_ticket;
+  __shared__ uint32_t s_ticket2;
+  // Keys of the tile after the current one, loaded straight into LDS: wave w
+  // owns entries [w * 64 * KPT, (w + 1) * 64 * KPT), filled by its 4 x 16-byte
+  // loads per lane (lane l's 16 bytes of load q at 16 * (q * 64 + l)).
+  constexpr bool kLdsPrefetch = PassCfg<THREADS>::kAgent && sizeof(K) == 4 && !VALS;
+  __shared__ __attribute__((aligned(16))) uint32_t s_next[kLdsPrefetch ? kTile : 4];
   // Used by the look-back agent only.
   constexpr bool kAgent = PassCfg<THREADS>::kAgent;
   __shared__ C s_lb_val[kAgent ? kThreads : 1];
@@ -343,14 +415,18 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
     return;
   }
 
-  // With an agent, the first ticket makes its workgroup the look-back agent
-  // and ticket t > 0 is tile t - 1; without, ticket t is tile t.
-  constexpr uint32_t kFirstTile = kAgent ? 1 : 0;
+  // With agents, the first kAgents tickets make their workgroups look-back
+  // agents and ticket t >= kAgents is tile t - kAgents; without, ticket t is
+  // tile t.
+  constexpr int kAgents = PassCfg<THREADS>::kAgents;
+  constexpr uint32_t kFirstTile = kAgents;
   if (tid == 0) s_ticket = atomicAdd(tile_counter, 1u);
   __syncthreads();
   if constexpr (kAgent) {
-    if (s_ticket == 0) {
-      lookback_agent<kThreads, C, S>(status_cur, num_tiles, s_lb_val, s_lb_used, s_doff, s_hist);
+    if (s_ticket < kFirstTile) {
+      constexpr int kDigits = kRadix / kAgents;
+      lookback_agent<kThreads, kDigits, PassCfg<THREADS>::kAgentW, C, S>(
+          status_cur, num_tiles, static_cast<int>(s_ticket) * kDigits, s_lb_val, s_lb_used, s_doff, s_hist);
       return;
     }
   }
@@ -365,20 +441,48 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
   const K in_flip = pp.first ? flip : K(0);  // intermediate buffers hold encoded keys
   const K out_flip = pp.last ? flip : K(0);
   const K pad = ~K(0) ^ in_flip;             // decodes to all-ones: sorts after every real key
+  const bool src_aligned = reinterpret_cast<uintptr_t>(src) % 16 == 0;
+
+  // This wave's prefetch slots: kKpt / 4 chunks of 64 lanes x 16 bytes.
+  uint32_t* const s_next_wave = s_next + (tid / kWave) * (kKpt / 4) * kWave * 4;
+
+  // Tickets run one tile ahead where keys are prefetched into LDS: `ahead`
+  // is the tile after the current one once known (kNone before).  Every
+  // workgroup holds the same lead, so tiles still start in ticket order.
+  constexpr uint32_t kNone = ~0u;
+  uint32_t ahead = kNone;
+  bool in_lds = false;  // the current tile's keys were prefetched into s_next
 
   K keys[kKpt];
   uint32_t vals[kKpt];  // unused (and optimised away) for key-only sorts
-  load_tile_keys<K, VALS, C, kKpt>(src, src_v, static_cast<C>(tile) * kTile + static_cast<C>(tid) * kKpt, n, pad,
-                                   keys, vals);
 
   while (true) {
     const C tile_base = static_cast<C>(tile) * kTile;
     if (status_next)
       for (int d = tid; d < kRadix; d += kThreads) status_next[static_cast<size_t>(tile) * kRadix + d] = 0;
     for (int d = tid; d < kRadix; d += kThreads) s_hist[d] = 0;
+    if constexpr (kLdsPrefetch) {
+      if (in_lds) {
+        // This wave's own prefetch, issued one tile ago: every thread has
+        // issued at least the previous (full) tile's kKpt stores since, so
+        // letting that many stay in flight still waits for the prefetch.
+        uint32_t raw[kKpt];
+        read_prefetched_keys<kKpt>(s_next_wave + (tid % kWave) * 4, raw);
 #pragma unroll
-    for (int j = 0; j < kKpt; ++j) keys[j] = flip_key(keys[j], in_flip);
-    __syncthreads();
+        for (int j = 0; j < kKpt; ++j) keys[j] = flip_key(static_cast<K>(raw[j]), in_flip);
+      } else {
+        load_tile_keys<K, VALS, C, kKpt>(src, src_v, tile_base + static_cast<C>(tid) * kKpt, n, pad, keys, vals);
+        // Finish these loads here, not where the two ways meet.
+#pragma unroll
+        for (int j = 0; j < kKpt; ++j) keys[j] = flip_key(keys[j], in_flip);
+        __builtin_amdgcn_s_waitcnt(waitcnt_vmcnt(0));
+      }
+    } else {
+      load_tile_keys<K, VALS, C, kKpt>(src, src_v, tile_base + static_cast<C>(tid) * kKpt, n, pad, keys, vals);
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j) keys[j] = flip_key(keys[j], in_flip);
+    }
+    lds_barrier();
 
     // Tile digit histogram.  When all keys of the wave share one digit (long
     // runs: sorted or skewed input) one lane adds them all, sparing the LDS
@@ -396,7 +500,7 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
         for (int j = 0; j < kKpt; ++j) atomicAdd(&s_hist[digit_of(keys[j], shift)], 1u);
       }
     }
-    __syncthreads();
+    lds_barrier();
 
     // Publish this tile's digit counts before sorting it.
     S* st = status_cur + static_cast<size_t>(tile) * kRadix + tid;
@@ -406,23 +510,70 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
       status_store(st, (tile == 0 ? St::kInc : St::kAgg) | static_cast<S>(cnt));
     }
 
+    // Prefetch the keys of the tile after this one into LDS while this tile
+    // is sorted (no registers held; nothing latency-critical queues behind
+    // the loads), and take the next ticket.
+    bool next_in_lds = false;
+    if constexpr (kLdsPrefetch) {
+      if (ahead != kNone && ahead < num_tiles && src_aligned &&
+          (static_cast<C>(ahead) + 1) * kTile <= n) {
+        const gptr<const K> from = src + static_cast<C>(ahead) * kTile + static_cast<C>(tid) * kKpt;
+#pragma unroll
+        for (int q = 0; q < kKpt / 4; ++q) global_to_lds_x4(from + 4 * q, s_next_wave + q * kWave * 4);
+        next_in_lds = true;
+      }
+    }
+    // atomicInc with the maximum bound is a fetch-and-add of one that the
+    // compiler leaves as a single atomic (its rewrite of a one-lane atomicAdd
+    // waits for the result right away, undoing the overlap).
+    uint32_t ticket = 0;
+    if (tid == 0) ticket = atomicInc(tile_counter, ~0u);
+
     // Sort the tile by the digit's low nibble.
     tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift, s_stage, s_vstage, s_counts, s_scan, true);
 
-    // Fetch the next ticket, and read the predecessor's word, while the
-    // second split runs: by the time the word is used the agent has usually
-    // published the predecessor's INCLUSIVE count.
-    uint32_t ticket = 0;
-    if (tid == 0) ticket = atomicAdd(tile_counter, 1u);
+    // A second ticket while the first tile runs, so that the lead is one tile
+    // from then on.
+    uint32_t ticket2 = 0;
+    const bool first_lead = kLdsPrefetch && ahead == kNone;
+    if (first_lead && tid == 0) ticket2 = atomicInc(tile_counter, ~0u);
+
+    // Read the predecessor's word while the second split runs: by the time it
+    // is used the agent has usually published the predecessor's INCLUSIVE count.
     S pred = 0;
     if (tid < kRadix && tile != 0) pred = status_load(st - kRadix);
 
     // ... and by the high nibble: the stage now holds the tile in digit order.
     tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift + kSubBits, s_stage, s_vstage, s_counts, s_scan, false);
 
-    if (tid == 0) s_ticket = ticket;
+    if (tid == 0) {
+      s_ticket = ticket;
+      s_ticket2 = ticket2;
+    }
     C tile_total;
     const C start = block_exclusive_scan_radix<kThreads>(static_cast<C>(cnt), s_cscan, &tile_total);
+
+    // Without LDS prefetch the tile's registers now take the next tile's
+    // keys: the loads land during the look-back.
+    uint32_t next;
+    if constexpr (kLdsPrefetch) {
+      if (ahead == kNone) {
+        next = s_ticket - kFirstTile;
+        ahead = s_ticket2 - kFirstTile;
+      } else {
+        next = ahead;
+        ahead = s_ticket - kFirstTile;
+      }
+    } else {
+      next = s_ticket - kFirstTile;
+    }
+    const bool more = next < num_tiles;
+    if constexpr (!kLdsPrefetch) {
+      if (more)
+        load_tile_keys<K, VALS, C, kKpt>(src, src_v, static_cast<C>(next) * kTile + static_cast<C>(tid) * kKpt, n,
+                                         pad, keys, vals);
+    }
+
     if (tid < kRadix) {
       C excl = 0;
       if (tile != 0) {
@@ -433,14 +584,7 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
       }
       s_doff[tid] = gbase[tid] + excl - start;
     }
-    __syncthreads();
-
-    // Start loading the next tile, then write this one out.
-    const uint32_t next = s_ticket - kFirstTile;
-    const bool more = next < num_tiles;
-    if (more)
-      load_tile_keys<K, VALS, C, kKpt>(src, src_v, static_cast<C>(next) * kTile + static_cast<C>(tid) * kKpt, n,
-                                       pad, keys, vals);
+    lds_barrier();
 
     const C remaining = n - tile_base;
     const int valid = remaining < static_cast<C>(kTile) ? static_cast<int>(remaining) : kTile;
@@ -453,8 +597,11 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
     }
     if (!more) break;
     tile = next;
-    __syncthreads();  // the stage, s_doff and s_hist are reused by the next tile
+    in_lds = next_in_lds;
+    lds_barrier();  // the stage, s_doff and s_hist are reused by the next tile
   }
+  // A prefetch is only issued for a tile this workgroup goes on to process,
+  // so none is in flight here.
 }
 
 // ---------------------------------------------------------------------------
@@ -563,11 +710,11 @@ ms_status launch_pass_t(uint64_t n, SortPlan* plan, int p, K flip, const C* gbas
                         hipStream_t s) {
   const uint64_t tiles = (n + PassCfg<THREADS>::kTile - 1) / PassCfg<THREADS>::kTile;
   // Persistent workgroups: as many as fit on the device at once (never more
-  // than tiles), plus the look-back agent where there is one.
+  // than tiles), plus the look-back agents.
   const uint64_t blocks =
       std::min<uint64_t>(tiles, resident_blocks(reinterpret_cast<const void*>(&onesweep_kernel<K, VALS, C, S, THREADS>),
                                                 THREADS, tiles)) +
-      (PassCfg<THREADS>::kAgent ? 1 : 0);
+      PassCfg<THREADS>::kAgents;
   MS_LAUNCH("onesweep_pass", (onesweep_kernel<K, VALS, C, S, THREADS>), static_cast<uint32_t>(blocks), THREADS, s,
             static_cast<const SortPlan*>(plan), p, static_cast<C>(n), flip, gbase, ctr, cur, next);
   return MS_OK;
@@ -579,7 +726,9 @@ template <typename K, bool VALS, int THREADS>
 constexpr int pass_lds_bytes() {
   constexpr int stage = padded16(PassCfg<THREADS>::kTile) * static_cast<int>(sizeof(K));
   constexpr int counts = SplitScratch<THREADS>::kCountWords * 4;
-  return (stage > counts ? stage : counts) + (VALS ? padded16(PassCfg<THREADS>::kTile) * 4 : 0) + 4096;
+  constexpr bool prefetch = PassCfg<THREADS>::kAgent && sizeof(K) == 4 && !VALS;
+  return (stage > counts ? stage : counts) + (VALS ? padded16(PassCfg<THREADS>::kTile) * 4 : 0) +
+         (prefetch ? PassCfg<THREADS>::kTile * 4 : 0) + (PassCfg<THREADS>::kAgent ? THREADS * 8 : 0) + 4096;
 }
 
 // 1,024-thread tiles are used for 32-bit keys without values, counted in

@@ -118,6 +118,13 @@ inline uint32_t __builtin_amdgcn_mbcnt_hi(uint32_t m, uint32_t acc) {
 inline uint32_t __builtin_amdgcn_readfirstlane(uint32_t v) { return static_cast<uint32_t>(simt::shfl_u64(v, 0)); }
 inline void __builtin_amdgcn_s_sleep(int) { simt::yield(); }
 inline void __builtin_amdgcn_wave_barrier() { simt::wave_sync(); }
+// Global-to-LDS load: lane l copies `size` bytes from its `src` to
+// dst + offset + l * size (dst is the same for every lane of the wave).  The
+// emulator copies at once, so waits for it are no-ops.
+inline void __builtin_amdgcn_global_load_lds(const void* src, void* dst, unsigned size, int offset, int) {
+  memcpy(static_cast<char*>(dst) + offset + simt::lane() * size, src, size);
+}
+inline void __builtin_amdgcn_s_waitcnt(int) {}
 // DPP move (GFX9 rules) for the controls the kernels use: row_shr:1..15
 // (0x111..0x11f, within rows of 16 lanes) and row_bcast:15 / row_bcast:31
 // (0x142 / 0x143).  Lanes of rows disabled by row_mask keep `old`; lanes
@@ -179,6 +186,14 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
 template <typename T>
 inline T atomicAdd(T* p, T v) {
   return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
+}
+// atomicInc: old = *p; *p = old >= bound ? 0 : old + 1; returns old.
+inline unsigned atomicInc(unsigned* p, unsigned bound) {
+  unsigned old = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+  while (!__atomic_compare_exchange_n(p, &old, old >= bound ? 0u : old + 1u, false, __ATOMIC_SEQ_CST,
+                                      __ATOMIC_SEQ_CST)) {
+  }
+  return old;
 }
 template <typename T>
 inline T atomicOr(T* p, T v) {

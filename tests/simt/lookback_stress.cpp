@@ -48,7 +48,7 @@ __global__ void stress_kernel(uint32_t* status, uint32_t* counter, const uint32_
   excl_out[tile * 64 + tid] = excl;
 }
 
-template <int THREADS>
+template <int THREADS, int kAgents, int kW>
 __global__ void agent_kernel(uint32_t* status, uint32_t* counter, const uint32_t* counts, uint32_t* excl_out,
                              uint32_t tiles, uint64_t* hits, uint64_t* walks) {
   using St = ms::Status<uint32_t>;
@@ -61,11 +61,13 @@ __global__ void agent_kernel(uint32_t* status, uint32_t* counter, const uint32_t
   const int tid = threadIdx.x;
   if (tid == 0) s_tile = atomicAdd(counter, 1u);
   __syncthreads();
-  if (s_tile == 0) {
-    ms::lookback_agent<THREADS, uint32_t, uint32_t>(status, tiles, s_val, s_used, s_prefix, s_next);
+  if (s_tile < kAgents) {
+    constexpr int kDigits = R / kAgents;
+    ms::lookback_agent<THREADS, kDigits, kW, uint32_t, uint32_t>(status, tiles, static_cast<int>(s_tile) * kDigits,
+                                                                 s_val, s_used, s_prefix, s_next);
     return;
   }
-  const uint32_t tile = s_tile - 1;
+  const uint32_t tile = s_tile - kAgents;
   if (tid >= R) return;
   uint32_t* st = status + tile * R + tid;
   const uint32_t cnt = counts[tile * R + tid];
@@ -88,15 +90,15 @@ __global__ void agent_kernel(uint32_t* status, uint32_t* counter, const uint32_t
   excl_out[tile * R + tid] = excl;
 }
 
-template <int THREADS>
+template <int THREADS, int kAgents, int kW>
 static int run_agent(int tiles) {
   constexpr int R = ms::kRadix;
   std::vector<uint32_t> status(tiles * R, 0), counts(tiles * R), excl(tiles * R, 0xffffffffu);
   uint32_t counter = 0;
   uint64_t hits = 0, walks = 0;
   for (int i = 0; i < tiles * R; ++i) counts[i] = mix(i + 999) % 1000;
-  hipLaunchKernelGGL((agent_kernel<THREADS>), dim3(tiles + 1), dim3(THREADS), 0, nullptr, status.data(), &counter,
-                     counts.data(), excl.data(), static_cast<uint32_t>(tiles), &hits, &walks);
+  hipLaunchKernelGGL((agent_kernel<THREADS, kAgents, kW>), dim3(tiles + kAgents), dim3(THREADS), 0, nullptr,
+                     status.data(), &counter, counts.data(), excl.data(), static_cast<uint32_t>(tiles), &hits, &walks);
   int bad = 0;
   for (int d = 0; d < R; ++d) {
     uint32_t run = 0, incl = 0;
@@ -110,8 +112,8 @@ static int run_agent(int tiles) {
   }
   // Both ways of finding the prefix must have been taken for the run to count.
   const bool covered = hits > 0 && walks > 0;
-  printf("%s lookback agent threads=%d tiles=%d wrong=%d predecessor-inclusive=%llu walked=%llu\n",
-         bad || !covered ? "FAIL" : "ok  ", THREADS, tiles, bad, static_cast<unsigned long long>(hits),
+  printf("%s lookback agents=%d threads=%d window=%d tiles=%d wrong=%d predecessor-inclusive=%llu walked=%llu\n",
+         bad || !covered ? "FAIL" : "ok  ", kAgents, THREADS, kW, tiles, bad, static_cast<unsigned long long>(hits),
          static_cast<unsigned long long>(walks));
   return bad || !covered ? 1 : 0;
 }
@@ -142,8 +144,8 @@ int main() {
   fails += run<1>(300);
   fails += run<8>(500);
   fails += run<16>(700);
-  fails += run_agent<256>(150);
-  fails += run_agent<512>(150);
-  fails += run_agent<1024>(150);
+  fails += run_agent<256, 1, 16>(150);
+  fails += run_agent<512, 2, 16>(150);
+  fails += run_agent<1024, 4, 8>(150);
   return fails ? 1 : 0;
 }
