@@ -16,7 +16,11 @@ JSON line:
                2^26 (uint64, uint32) pairs, the paper's 10^5-key p = 4 method,
                and a copy-kernel HBM probe
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu] [--no-tune]
+
+--no-tune runs the library's default launch parameters instead of timing
+candidates first (profiling runs use it, so that only the measured kernels
+appear in the trace).
 """
 from __future__ import annotations
 
@@ -33,7 +37,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 METRIC = "GKeys/s at 2^28 int32 vs HBM roofline; p50/p99 latency of batched sorts"
 DOMINANT = "onesweep_pass"
-PMC_FILE = os.path.join(ROOT, "profiles", "onesweep_pass_2p28_i32_pmc.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "onesweep_pass_2p28_i32_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1105_6040_amd", "csrc", "radix.hip")
 
 
@@ -108,6 +112,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (no multi-GPU path is built)",
@@ -138,10 +143,12 @@ def main():
     copy_probe = {"bytes_per_launch": 2 * n * 4, "ms_median": round(sorted(cper)[len(cper) // 2], 4),
                   "GBps": round(2 * n * 4 / (sorted(cper)[len(cper) // 2] * 1e-3) / 1e9, 1)}
 
-    log("autotuning the headline sort")
     from paper_1105_6040_amd import tune
-    tuner = tune.Tuner(cache_path=None, reps=3)
-    tuned = tuner.tune_sort(keys)
+    if args.no_tune:
+        tuned = {"params": [N.tune_get(N.MS_TUNE_PASS_THREADS), N.tune_get(N.MS_TUNE_HIST_BLOCKS)], "trials": []}
+    else:
+        log("autotuning the headline sort")
+        tuned = tune.Tuner(cache_path=None, reps=3).tune_sort(keys)
     log("timing headline")
     N.timing_reset()
     for _ in range(args.warmup):

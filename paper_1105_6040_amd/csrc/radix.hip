@@ -774,7 +774,7 @@ ms_status run_onesweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
   const uint64_t per_block = 256ull * 16;
   uint64_t hblocks = (n + per_block - 1) / per_block;
-  const int64_t hmax = tune_get(MS_TUNE_HIST_BLOCKS) > 0 ? tune_get(MS_TUNE_HIST_BLOCKS) : 1024;
+  const int64_t hmax = tune_get(MS_TUNE_HIST_BLOCKS) > 0 ? tune_get(MS_TUNE_HIST_BLOCKS) : 512;
   if (hblocks > static_cast<uint64_t>(hmax)) hblocks = static_cast<uint64_t>(hmax);
   MS_LAUNCH("histogram", (histogram_kernel<K, C>), static_cast<uint32_t>(hblocks), 256, s,
             static_cast<const K*>(kin), static_cast<C>(n), flip, ghist, gbase, ctrs, plan, buf, VALS ? 1 : 0);
