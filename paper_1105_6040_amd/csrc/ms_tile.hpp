@@ -37,7 +37,8 @@ struct SplitScratch {
 };
 
 // Block-wide exclusive scan of one uint32 per thread; `scratch` holds
-// THREADS / 64 words.  Contains barriers.
+// THREADS / 64 words.  Contains a barrier; the caller must pass another one
+// before the next call (the scratch is read until then).
 template <int THREADS>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch) {
   constexpr int kWaves = THREADS / kWave;
@@ -50,7 +51,8 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 #pragma unroll
   for (int w = 0; w < kWaves; ++w)
     if (w < wave) base += scratch[w];
-  lds_barrier();
+  // No barrier after the reads: the caller meets one before `scratch` is
+  // written again.
   return base + incl - v;
 }
 

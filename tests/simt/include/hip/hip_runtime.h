@@ -182,6 +182,20 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
   return out;
 }
 
+template <typename T>
+inline T __shfl(T v, int src_lane, int width = 64) {
+  if (width != 64) {
+    fprintf(stderr, "simt: only full-wave __shfl is emulated\n");
+    abort();
+  }
+  uint64_t bits = 0;
+  memcpy(&bits, &v, sizeof(T));
+  const uint64_t got = simt::shfl_u64(bits, src_lane & 63);
+  T out;
+  memcpy(&out, &got, sizeof(T));
+  return out;
+}
+
 // Atomics: blocks run on parallel OS threads, so real atomics.
 template <typename T>
 inline T atomicAdd(T* p, T v) {
