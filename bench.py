@@ -17,6 +17,7 @@ JSON line:
                and a copy-kernel HBM probe
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu] [--no-tune]
+       python bench.py --psweep    (the process-count sweep instead of the headline)
 
 --no-tune runs the library's default launch parameters instead of timing
 candidates first (profiling runs use it, so that only the measured kernels
@@ -113,6 +114,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--psweep", action="store_true",
+                    help="instead of the headline: the process-count sweep (paper's method, p = 1..64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (no multi-GPU path is built)",
@@ -127,6 +130,9 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if args.psweep:
+        print(json.dumps(process_sweep(dev, stream)), flush=True)
+        return
     n = 1 << 28
     log("generating 2^28 int32 uniform keys")
     keys_np = inputs.keys_2p28("uniform", seed=0)
@@ -207,7 +213,6 @@ def extra_workloads(args, dev, stream, keys_u, keys_u_np):
     import numpy as np
     import torch
 
-    import oracle
     from paper_1105_6040_amd import _native as N
     from paper_1105_6040_amd import api, inputs
 
@@ -246,8 +251,7 @@ def extra_workloads(args, dev, stream, keys_u, keys_u_np):
 
     log("paper method 10^5, p = 4")
     k_np, p = inputs.paper_small(0)
-    off = oracle.part_offsets(k_np.size, p)
-    k, toff = torch.from_numpy(k_np).to(dev), torch.from_numpy(off).to(dev)
+    k, toff = torch.from_numpy(k_np).to(dev), api.part_offsets(k_np.size, p, dev)
     s_out, m_out = torch.empty_like(k), torch.empty_like(k)
 
     def paper():
@@ -256,12 +260,57 @@ def extra_workloads(args, dev, stream, keys_u, keys_u_np):
     wall, per = time_steps(paper, 100, 10, stream)
     ex["paper_small_p4"] = {"us_median": round(sorted(per)[len(per) // 2] * 1e3, 1),
                             "us_p99": round(percentile(per, 99) * 1e3, 1)}
-    assert np.array_equal(m_out.cpu().numpy(), oracle.paper_method(k_np, p))
+    # The paper's method (parts sorted, then merged) must give the whole-list sort.
+    assert torch.equal(m_out, api.sort_keys(k)), "paper method differs from sort_keys"
     del k, toff, s_out, m_out
 
     ex["segments_50k"] = segments_workload(dev, stream)
     ex["serving"] = serving_workload(dev)
     return ex
+
+
+def process_sweep(dev, stream, reps=20, warmup=5):
+    """The paper's Experiment 1 on the GPU: a list of n int32 keys (2*10^5 and
+    6*10^6, Table 1's sizes) split into p = 1, 2, 4, ..., 64 contiguous parts,
+    each part sorted (sort_segmented, one launch for all parts), then the p
+    sorted parts merged (merge_runs).  Median of `reps` HIP-event-timed runs
+    per phase; every result must equal sort_keys on the whole list."""
+    import numpy as np
+    import torch
+
+    from paper_1105_6040_amd import api, inputs
+
+    rows = []
+    for n in (200_000, 6_000_000):
+        log(f"process sweep n={n}")
+        k = torch.from_numpy(inputs.process_sweep_keys(n, 0)).to(dev)
+        ref = api.sort_keys(k)
+        s_out, m_out = torch.empty_like(k), torch.empty_like(k)
+        _, whole = time_steps(lambda: api.sort_keys(k, out=s_out), reps, warmup, stream)
+        for p in (1, 2, 4, 8, 16, 32, 64):
+            off = api.part_offsets(n, p, dev)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            sort_ms, merge_ms = [], []
+            for it in range(warmup + reps):
+                ev[0].record(stream)
+                api.sort_segmented(k, off, keys_out=s_out)
+                ev[1].record(stream)
+                api.merge_runs(s_out, off, keys_out=m_out)
+                ev[2].record(stream)
+                torch.cuda.synchronize()
+                if it >= warmup:
+                    sort_ms.append(ev[0].elapsed_time(ev[1]))
+                    merge_ms.append(ev[1].elapsed_time(ev[2]))
+            assert torch.equal(m_out, ref), f"paper method differs from sort_keys at n={n}, p={p}"
+            med = lambda xs: sorted(xs)[len(xs) // 2]  # noqa: E731
+            rows.append({"n": n, "p": p, "sort_phase_us": round(med(sort_ms) * 1e3, 1),
+                         "merge_phase_us": round(med(merge_ms) * 1e3, 1),
+                         "total_us": round(med([a + b for a, b in zip(sort_ms, merge_ms)]) * 1e3, 1),
+                         "sort_keys_whole_list_us": round(med(whole) * 1e3, 1)})
+            log(rows[-1])
+        del k, ref, s_out, m_out
+    return {"experiment": "process-count sweep (paper's Experiment 1, Table 1 sizes)", "unit": "us",
+            "data": "synthetic int32 uniform [0, 2^31), seed 0", "rows": rows}
 
 
 def segments_workload(dev, stream, seed=0):

@@ -134,7 +134,8 @@ const char *ms_last_error(void);
  *   MS_TUNE_SEG_BLOCKS    persistent workgroups of sort_segmented (1 .. 65536;
  *                         0 = the default, 1024).
  *   MS_TUNE_HIST_BLOCKS   workgroups of the digit-histogram read of sort_keys /
- *                         sort_pairs (1 .. 65536; 0 = the default, 512).
+ *                         sort_pairs (1 .. 65536; 0 = the default, one per
+ *                         compute unit).
  * ms_tune_set returns MS_EINVAL for an unknown parameter or value;
  * ms_tune_get returns the current value (0 for an unknown parameter).
  */

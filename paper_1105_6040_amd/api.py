@@ -106,6 +106,20 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, keys_out: Optional[torch.
     return keys_out, vals_out
 
 
+def part_offsets(n: int, p: int, device=None) -> torch.Tensor:
+    """Scatter phase (Figure 1): split a list of n items into p contiguous
+    parts of about n/p items; part i = [floor(i*n/p), floor((i+1)*n/p)), so
+    part sizes differ by at most one when p does not divide n.  Returns the
+    p + 1 boundaries as a uint64 tensor (on `device` if given), ready for
+    sort_segmented and merge_runs.  No data moves."""
+    if p < 1:
+        raise ValueError(f"part_offsets: p must be at least 1 (got {p})")
+    if n < 0:
+        raise ValueError(f"part_offsets: n must be non-negative (got {n})")
+    off = torch.tensor([(i * n) // p for i in range(p + 1)], dtype=torch.uint64)
+    return off if device is None else off.to(device)
+
+
 def sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, vals: Optional[torch.Tensor] = None,
                    keys_out: Optional[torch.Tensor] = None, vals_out: Optional[torch.Tensor] = None,
                    ws: Optional[torch.Tensor] = None):

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void histogram_kernel(const K* __restrict__ ke
                                                         uint32_t* done, SortPlan* plan, Buffers buf,
                                                         int has_vals) {
   constexpr int P = sizeof(K);        // 8-bit digits
-  constexpr int kCopies = 32 / P;     // counter copies spread same-digit lanes: 32 KB of LDS
+  constexpr int kCopies = 64 / P;     // counter copies spread same-digit lanes: 64 KB of LDS
   constexpr int kVec = 16 / sizeof(K);
   __shared__ uint32_t h[P * kRadix * kCopies];
   __shared__ C s_scan[kRadix / kWave];
@@ -153,12 +153,31 @@ __global__ __launch_bounds__(256) void histogram_kernel(const K* __restrict__ ke
   const uint4* vbase = reinterpret_cast<const uint4*>(keys + head);
   const C stride = static_cast<C>(gridDim.x) * 256;
   C i = static_cast<C>(blockIdx.x) * 256 + tid;
-  for (; i + 3 * stride < nvec; i += 4 * stride) {
-    const uint4 v0 = vbase[i], v1 = vbase[i + stride], v2 = vbase[i + 2 * stride], v3 = vbase[i + 3 * stride];
-    count_vec(v0);
-    count_vec(v1);
-    count_vec(v2);
-    count_vec(v3);
+  // Four vectors per thread per step; the next step's loads are issued
+  // before this step's counting, so the LDS atomics overlap the HBM latency.
+  if (i + 3 * stride < nvec) {
+    uint4 a0 = vbase[i], a1 = vbase[i + stride], a2 = vbase[i + 2 * stride], a3 = vbase[i + 3 * stride];
+    for (;;) {
+      const C nxt = i + 4 * stride;
+      const bool more = nxt + 3 * stride < nvec;
+      uint4 b0 = a0, b1 = a1, b2 = a2, b3 = a3;
+      if (more) {
+        b0 = vbase[nxt];
+        b1 = vbase[nxt + stride];
+        b2 = vbase[nxt + 2 * stride];
+        b3 = vbase[nxt + 3 * stride];
+      }
+      count_vec(a0);
+      count_vec(a1);
+      count_vec(a2);
+      count_vec(a3);
+      i = nxt;
+      if (!more) break;
+      a0 = b0;
+      a1 = b1;
+      a2 = b2;
+      a3 = b3;
+    }
   }
   for (; i < nvec; i += stride) count_vec(vbase[i]);
   if (blockIdx.x == 0) {
@@ -705,6 +724,17 @@ uint64_t resident_blocks(const void* kernel, int threads, uint64_t fallback) {
   return blocks;
 }
 
+// Compute units of the current device (`fallback` when the runtime cannot say).
+uint64_t device_cus(uint64_t fallback) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+    (void)hipGetLastError();
+    return fallback;
+  }
+  return static_cast<uint64_t>(cus);
+}
+
 template <typename K, bool VALS, typename C, typename S, int THREADS>
 ms_status launch_pass_t(uint64_t n, SortPlan* plan, int p, K flip, const C* gbase, uint32_t* ctr, S* cur, S* next,
                         hipStream_t s) {
@@ -774,8 +804,11 @@ ms_status run_onesweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
   const uint64_t per_block = 256ull * 16;
   uint64_t hblocks = (n + per_block - 1) / per_block;
-  const int64_t hmax = tune_get(MS_TUNE_HIST_BLOCKS) > 0 ? tune_get(MS_TUNE_HIST_BLOCKS) : 512;
-  if (hblocks > static_cast<uint64_t>(hmax)) hblocks = static_cast<uint64_t>(hmax);
+  // One workgroup per CU by default: the read is bound by the LDS atomics,
+  // and a second workgroup per CU only adds its clearing and flushing.
+  const int64_t tuned = tune_get(MS_TUNE_HIST_BLOCKS);
+  const uint64_t hmax = tuned > 0 ? static_cast<uint64_t>(tuned) : device_cus(256);
+  if (hblocks > hmax) hblocks = hmax;
   MS_LAUNCH("histogram", (histogram_kernel<K, C>), static_cast<uint32_t>(hblocks), 256, s,
             static_cast<const K*>(kin), static_cast<C>(n), flip, ghist, gbase, ctrs, plan, buf, VALS ? 1 : 0);
 

@@ -22,7 +22,7 @@ from __future__ import annotations
 import numpy as np
 
 WORKLOAD_IDS = {"paper_small": 1, "keys_2p28": 2, "pairs_2p26": 3, "segments": 4, "serving": 5,
-                "unit": 9}
+                "process_sweep": 6, "unit": 9}
 
 DTYPES = {"i32": np.int32, "u32": np.uint32, "u64": np.uint64}
 
@@ -85,6 +85,13 @@ def paper_small(seed: int = 0):
     """100,000 int32 keys uniform in [0, 2^31) and p = 4 (the paper's method, small)."""
     g = rng("paper_small", seed)
     return g.integers(0, 2**31, 100_000, dtype=np.int32), 4
+
+
+def process_sweep_keys(n: int, seed: int = 0) -> np.ndarray:
+    """n int32 keys uniform in [0, 2^31): the lists of the process-count sweep
+    (the paper's Experiment 1 sorts 2*10^5 and 6*10^6 items)."""
+    g = np.random.default_rng([WORKLOAD_IDS["process_sweep"], int(n), int(seed)])
+    return g.integers(0, 2**31, n, dtype=np.int32)
 
 
 def keys_2p28(dist: str = "uniform", seed: int = 0, n: int = 2**28) -> np.ndarray:

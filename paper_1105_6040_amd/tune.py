@@ -30,7 +30,7 @@ DEFAULT_CACHE = os.environ.get("MI355SORT_TUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "mi355sort", "tune.json"))
 
 PASS_THREADS = (256, 512, 1024)
-HIST_BLOCKS = (256, 512, 1024, 2048)
+HIST_BLOCKS = (128, 256, 512, 1024)
 SEG_BLOCKS = (256, 512, 1024, 2048)
 SERVE_THRESHOLDS = (1 << 13, 1 << 16, 1 << 18)
 

@@ -96,6 +96,30 @@ def test_every_tile_size(threads):
         N.tune_set(N.MS_TUNE_PASS_THREADS, old)
 
 
+@pytest.mark.parametrize("dt", ["i32", "u32"])
+def test_single_block_histogram(dt):
+    """The whole digit-histogram read done by one workgroup (each of its
+    counters then sees every key of its lane class).  Nearly all keys are
+    equal, so one bin of every digit position takes almost every key; the
+    view starts one key in, so the unaligned head and the tail are counted
+    too.  Closed form: each distinct key, ascending, repeated by its count."""
+    from paper_1105_6040_amd import _native as N
+    old = N.tune_get(N.MS_TUNE_HIST_BLOCKS)
+    N.tune_set(N.MS_TUNE_HIST_BLOCKS, 1)
+    try:
+        n = (1 << 24) + 3
+        g = np.random.default_rng(11)
+        ty = np.int32 if dt == "i32" else np.uint32
+        k = np.full(n, 0x5A5A5A5A, dtype=ty)
+        k[g.integers(0, n, 1000)] = g.integers(-(2**31) if dt == "i32" else 0, 2**31, 1000).astype(ty)
+        say(f"single-block histogram {dt}: sorting")
+        out = host(api.sort_keys(dev(k)[1:]))
+        vals, counts = np.unique(k[1:], return_counts=True)
+        assert np.array_equal(out, np.repeat(vals, counts)), dt
+    finally:
+        N.tune_set(N.MS_TUNE_HIST_BLOCKS, old)
+
+
 def test_repeat_determinism_low_bits():
     """The same pairs sorted 25 times give the oracle's answer every time
     (12-bit keys: two constant digit bytes, many ties)."""
@@ -180,12 +204,31 @@ def test_merge_runs_parity(dt, nruns):
 def test_paper_method_small():
     """100,000 int32 keys, p = 4 equal parts: sort each part, merge (Figure 1)."""
     k, p = inputs.paper_small(0)
-    off = oracle.part_offsets(k.size, p)
+    off = api.part_offsets(k.size, p, "cuda")
+    assert np.array_equal(host(off), oracle.part_offsets(k.size, p))
     v = np.arange(k.size, dtype=np.uint32)
-    sk, sv = api.sort_segmented(dev(k), dev(off), dev(v))
-    mk, mv = api.merge_runs(sk, dev(off), sv)
+    sk, sv = api.sort_segmented(dev(k), off, dev(v))
+    mk, mv = api.merge_runs(sk, off, sv)
     ek, ev = oracle.paper_method(k, p, v)
     assert np.array_equal(host(mk), ek) and np.array_equal(host(mv), ev)
+
+
+@pytest.mark.parametrize("n", [20001, 200000])
+def test_paper_method_process_sweep(n):
+    """The paper's method for every process count of its Experiment 1
+    (p = 1, 2, 4, ..., 64, Table 1) on pairs: parts sorted by sort_segmented,
+    then merged by merge_runs, against the oracle's stable sort."""
+    g = np.random.default_rng(n)
+    k = g.integers(0, 2**31, n, dtype=np.int64).astype(np.int32)
+    v = np.arange(n, dtype=np.uint32)
+    ek, ev = oracle.sort(k, v)
+    tk, tv = dev(k), dev(v)
+    for p in (1, 2, 4, 8, 16, 32, 64):
+        say(f"process sweep n={n} p={p}")
+        off = api.part_offsets(n, p, "cuda")
+        sk, sv = api.sort_segmented(tk, off, tv)
+        mk, mv = api.merge_runs(sk, off, sv)
+        assert np.array_equal(host(mk), ek) and np.array_equal(host(mv), ev), (n, p)
 
 
 # ---------------------------------------------------------------------------- full sizes
