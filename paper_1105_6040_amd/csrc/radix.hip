@@ -343,7 +343,7 @@ __device__ __forceinline__ void read_prefetched_keys(const uint32_t* lane_src, u
 template <typename K, bool VALS, typename C, int KPT>
 __device__ __forceinline__ void load_tile_keys(gptr<const K> src, gptr<const uint32_t> src_v, C my_base, C n, K pad,
                                                K (&keys)[KPT], uint32_t (&vals)[KPT]) {
-  const bool vec_ok = (reinterpret_cast<uintptr_t>(src) % 16 == 0) && my_base + KPT <= n;
+  const bool vec_ok = (reinterpret_cast<uintptr_t>(src + my_base) % 16 == 0) && my_base + KPT <= n;
   if (vec_ok) {
     constexpr int kPer = 16 / sizeof(K);
     gptr<const uint4> p4 = (gptr<const uint4>)(src + my_base);
@@ -368,7 +368,7 @@ __device__ __forceinline__ void load_tile_keys(gptr<const K> src, gptr<const uin
     }
   }
   if constexpr (VALS) {
-    const bool vvec = (reinterpret_cast<uintptr_t>(src_v) % 16 == 0) && my_base + KPT <= n;
+    const bool vvec = (reinterpret_cast<uintptr_t>(src_v + my_base) % 16 == 0) && my_base + KPT <= n;
     if (vvec) {
       gptr<const uint4> p4 = (gptr<const uint4>)(src_v + my_base);
 #pragma unroll
@@ -624,6 +624,273 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// 5. The digit passes of sort_segmented for a few long segments: the paper's
+// parts sorted by the whole device at once instead of one workgroup each.
+//
+// Every segment is cut into kTile-key tiles from its own start (its last tile
+// is partial) and the tiles of all segments are numbered in segment order.  A
+// tile takes its digit bases from its own segment's histograms, and the
+// segment's first tile publishes INCLUSIVE at once, so that the look-back of
+// every other tile ends inside its segment.  All passes run (no trivial-pass
+// skip): even P ping-pongs keys_in -> workspace -> keys_out -> ... -> keys_out.
+constexpr int kSegSweepThreads = 512;
+constexpr uint32_t kSegSweepMaxSegments = 1024;
+// Used when the segments average more keys than one workgroup sorts in LDS
+// (8,192): shorter ones are sorted faster by one workgroup each.
+constexpr uint64_t kSegSweepMinAverage = 8192;
+using SegSweepCfg = PassCfg<kSegSweepThreads>;
+
+// Segment of tile t: the s with tile_start[s] <= t < tile_start[s + 1]
+// (a non-empty segment; tile_start[nseg] is the tile count, above t).
+__device__ __forceinline__ uint32_t segment_of_tile(const uint32_t* tile_start, uint32_t nseg, uint32_t t) {
+  uint32_t lo = 0, hi = nseg;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (tile_start[mid] <= t)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Tile table and pass plan (one block of 1,024 threads, nseg <= 1,024).
+template <typename K, bool VALS>
+__global__ __launch_bounds__(1024) void segsweep_plan_kernel(const uint64_t* __restrict__ off, uint32_t nseg,
+                                                             uint32_t* __restrict__ tile_start, SortPlan* plan,
+                                                             Buffers buf) {
+  constexpr int kTile = SegSweepCfg::kTile;
+  constexpr int P = sizeof(K);
+  __shared__ uint32_t s_scan[1024 / kWave];
+  const int tid = threadIdx.x;
+  const uint32_t tiles =
+      static_cast<uint32_t>(tid) < nseg ? static_cast<uint32_t>((off[tid + 1] - off[tid] + kTile - 1) / kTile) : 0u;
+  const uint32_t start = block_exclusive_scan<1024>(tiles, s_scan);
+  if (static_cast<uint32_t>(tid) < nseg) tile_start[tid] = start;
+  if (static_cast<uint32_t>(tid) == nseg - 1) tile_start[nseg] = start + tiles;
+  if (tid != 0) return;
+  for (int p = 0; p < kMaxPasses; ++p) {
+    PassPlan pp = {};
+    if (p < P) {
+      const bool to_out = p % 2 == 1;
+      pp.src_k = p == 0 ? buf.keys_in : (to_out ? buf.alt_k : buf.keys_out);
+      pp.dst_k = to_out ? buf.keys_out : buf.alt_k;
+      pp.src_v = p == 0 ? buf.vals_in : (to_out ? buf.alt_v : buf.vals_out);
+      pp.dst_v = VALS ? (to_out ? buf.vals_out : buf.alt_v) : nullptr;
+      pp.active = 1;
+      pp.first = p == 0;
+      pp.last = p == P - 1;
+    }
+    plan->pass[p] = pp;
+  }
+  plan->copy = 0;
+  plan->copy_src_k = nullptr;
+  plan->copy_dst_k = nullptr;
+  plan->copy_src_v = nullptr;
+  plan->copy_dst_v = nullptr;
+  plan->num_active = P;
+}
+
+// Digit histograms of every segment (all P digit positions): each block
+// counts a contiguous range of tiles in LDS and adds its counts to the
+// segment's row whenever the segment changes.
+template <typename K, typename C>
+__global__ __launch_bounds__(256) void segsweep_hist_kernel(const K* __restrict__ keys, K flip,
+                                                            const uint64_t* __restrict__ off, uint32_t nseg,
+                                                            const uint32_t* __restrict__ tile_start,
+                                                            C* __restrict__ seg_hist) {
+  constexpr int P = sizeof(K);
+  constexpr int kCopies = 64 / P;
+  constexpr int kTile = SegSweepCfg::kTile;
+  __shared__ uint32_t h[P * kRadix * kCopies];
+  __shared__ uint32_t s_tstart[kSegSweepMaxSegments + 1];
+  const int tid = threadIdx.x;
+  for (uint32_t i = tid; i <= nseg; i += 256) s_tstart[i] = tile_start[i];
+  for (int i = tid; i < P * kRadix * kCopies; i += 256) h[i] = 0;
+  __syncthreads();
+  const uint32_t total = s_tstart[nseg];
+  const uint32_t t0 = static_cast<uint32_t>(static_cast<uint64_t>(total) * blockIdx.x / gridDim.x);
+  const uint32_t t1 = static_cast<uint32_t>(static_cast<uint64_t>(total) * (blockIdx.x + 1) / gridDim.x);
+  const uint32_t copy = lane_id() % kCopies;
+  auto flush = [&](uint32_t s) {
+    __syncthreads();
+    for (int b = tid; b < P * kRadix; b += 256) {
+      uint32_t sum = 0;
+#pragma unroll
+      for (int c = 0; c < kCopies; ++c) {
+        sum += h[b * kCopies + c];
+        h[b * kCopies + c] = 0;
+      }
+      if (sum) atomic_add_c(&seg_hist[static_cast<size_t>(s) * P * kRadix + b], static_cast<C>(sum));
+    }
+    __syncthreads();
+  };
+  uint32_t cur = ~0u;
+  for (uint32_t t = t0; t < t1; ++t) {
+    const uint32_t s = segment_of_tile(s_tstart, nseg, t);
+    if (s != cur && cur != ~0u) flush(cur);
+    cur = s;
+    const uint64_t b = off[s] + static_cast<uint64_t>(t - s_tstart[s]) * kTile;
+    const uint64_t e = b + kTile < off[s + 1] ? b + kTile : off[s + 1];
+    for (uint64_t i = b + tid; i < e; i += 256) {
+      const K k = flip_key(keys[i], flip);
+#pragma unroll
+      for (int p = 0; p < P; ++p) atomicAdd(&h[(p * kRadix + digit_of(k, 8 * p)) * kCopies + copy], 1u);
+    }
+  }
+  if (cur != ~0u) flush(cur);
+}
+
+// Digit bases: row (s, p) of seg_base = off[s] + exclusive scan of the
+// segment's digit-p counts.  One block per row.
+template <typename C>
+__global__ __launch_bounds__(256) void segsweep_base_kernel(const uint64_t* __restrict__ off, int P,
+                                                            const C* __restrict__ seg_hist, C* __restrict__ seg_base) {
+  __shared__ C s_scan[kRadix / kWave];
+  const uint32_t row = blockIdx.x;
+  const C c = seg_hist[static_cast<size_t>(row) * kRadix + threadIdx.x];
+  C total;
+  const C ex = block_exclusive_scan_radix<256>(c, s_scan, &total);
+  seg_base[static_cast<size_t>(row) * kRadix + threadIdx.x] = static_cast<C>(off[row / P]) + ex;
+}
+
+// One digit pass over the tiles of every segment (persistent workgroups,
+// tiles by ticket as in onesweep_kernel, without agents or LDS prefetch).
+template <typename K, bool VALS, typename C, typename S>
+__global__ __launch_bounds__(kSegSweepThreads) void segsweep_pass_kernel(
+    const SortPlan* __restrict__ plan, int pass, const uint64_t* __restrict__ off, uint32_t nseg,
+    const uint32_t* __restrict__ tile_start, K flip, const C* __restrict__ seg_base, uint32_t* tile_counter,
+    S* status_cur, S* status_next) {
+  constexpr int kThreads = kSegSweepThreads;
+  constexpr int kKpt = SegSweepCfg::kKpt;
+  constexpr int kTile = SegSweepCfg::kTile;
+  constexpr int P = sizeof(K);
+  using St = Status<S>;
+
+  constexpr int kStageBytes = padded16(kTile) * static_cast<int>(sizeof(K));
+  constexpr int kCountBytes = SplitScratch<kThreads>::kCountWords * 4;
+  __shared__ __attribute__((aligned(16))) uint8_t s_raw[kStageBytes > kCountBytes ? kStageBytes : kCountBytes];
+  K* s_stage = reinterpret_cast<K*>(s_raw);
+  uint32_t* s_counts = reinterpret_cast<uint32_t*>(s_raw);
+  __shared__ uint32_t s_vstage[VALS ? padded16(kTile) : 1];
+  __shared__ uint32_t s_hist[kRadix];
+  __shared__ C s_doff[kRadix];
+  __shared__ uint32_t s_scan[kThreads / kWave];
+  __shared__ C s_cscan[kRadix / kWave];
+  __shared__ uint32_t s_ticket;
+  __shared__ uint32_t s_tstart[kSegSweepMaxSegments + 1];
+
+  const int tid = threadIdx.x;
+  for (uint32_t i = tid; i <= nseg; i += kThreads) s_tstart[i] = tile_start[i];
+  if (tid == 0) s_ticket = atomicAdd(tile_counter, 1u);
+  __syncthreads();
+  const uint32_t num_tiles = s_tstart[nseg];
+  uint32_t tile = s_ticket;
+  if (tile >= num_tiles) return;
+
+  const PassPlan& pp = plan->pass[pass];
+  const int shift = 8 * pass;
+  const gptr<const K> src = as_global(static_cast<const K*>(pp.src_k));
+  const gptr<const uint32_t> src_v = as_global(static_cast<const uint32_t*>(pp.src_v));
+  const gptr<K> dst = as_global(static_cast<K*>(pp.dst_k));
+  const gptr<uint32_t> dst_v = as_global(pp.dst_v);
+  const K in_flip = pp.first ? flip : K(0);
+  const K out_flip = pp.last ? flip : K(0);
+  const K pad = ~K(0) ^ in_flip;  // decodes to all-ones: sorts after every real key of the tile
+
+  // The tile's segment, its index in the segment, first key and the
+  // segment's end.
+  uint32_t seg = segment_of_tile(s_tstart, nseg, tile);
+  uint32_t j = tile - s_tstart[seg];
+  C tile_base = static_cast<C>(off[seg]) + static_cast<C>(j) * kTile;
+  C seg_end = static_cast<C>(off[seg + 1]);
+
+  K keys[kKpt];
+  uint32_t vals[kKpt];
+  load_tile_keys<K, VALS, C, kKpt>(src, src_v, tile_base + static_cast<C>(tid) * kKpt, seg_end, pad, keys, vals);
+
+  while (true) {
+#pragma unroll
+    for (int q = 0; q < kKpt; ++q) keys[q] = flip_key(keys[q], in_flip);
+    if (status_next)
+      for (int d = tid; d < kRadix; d += kThreads) status_next[static_cast<size_t>(tile) * kRadix + d] = 0;
+    for (int d = tid; d < kRadix; d += kThreads) s_hist[d] = 0;
+    lds_barrier();
+
+    {
+      const uint32_t d0 = digit_of(keys[0], shift);
+      bool same = true;
+#pragma unroll
+      for (int q = 1; q < kKpt; ++q) same = same && digit_of(keys[q], shift) == d0;
+      const uint32_t w0 = __builtin_amdgcn_readfirstlane(d0);
+      if (__builtin_amdgcn_ballot_w64(same && d0 == w0) == ~0ull) {
+        if (lane_id() == 0) atomicAdd(&s_hist[w0], static_cast<uint32_t>(kWave * kKpt));
+      } else {
+#pragma unroll
+        for (int q = 0; q < kKpt; ++q) atomicAdd(&s_hist[digit_of(keys[q], shift)], 1u);
+      }
+    }
+    lds_barrier();
+
+    // A segment's first tile has no predecessor in its segment.
+    S* st = status_cur + static_cast<size_t>(tile) * kRadix + tid;
+    uint32_t cnt = 0;
+    if (tid < kRadix) {
+      cnt = s_hist[tid];
+      status_store(st, (j == 0 ? St::kInc : St::kAgg) | static_cast<S>(cnt));
+    }
+    uint32_t ticket = 0;
+    if (tid == 0) ticket = atomicInc(tile_counter, ~0u);
+
+    tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift, s_stage, s_vstage, s_counts, s_scan, true);
+    S pred = 0;
+    if (tid < kRadix && j != 0) pred = status_load(st - kRadix);
+    tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift + kSubBits, s_stage, s_vstage, s_counts, s_scan, false);
+
+    if (tid == 0) s_ticket = ticket;
+    C tile_total;
+    const C start = block_exclusive_scan_radix<kThreads>(static_cast<C>(cnt), s_cscan, &tile_total);
+
+    // The next tile's keys load into the registers during the look-back.
+    const uint32_t next = s_ticket;
+    const bool more = next < num_tiles;
+    const uint32_t cur_seg = seg, cur_j = j;
+    const C cur_base = tile_base, cur_end = seg_end;
+    if (more) {
+      seg = segment_of_tile(s_tstart, nseg, next);
+      j = next - s_tstart[seg];
+      tile_base = static_cast<C>(off[seg]) + static_cast<C>(j) * kTile;
+      seg_end = static_cast<C>(off[seg + 1]);
+      load_tile_keys<K, VALS, C, kKpt>(src, src_v, tile_base + static_cast<C>(tid) * kKpt, seg_end, pad, keys, vals);
+    }
+
+    if (tid < kRadix) {
+      C excl = 0;
+      if (cur_j != 0) {
+        excl = (pred & St::kFlagMask) == St::kInc ? static_cast<C>(pred & St::kValMask)
+                                                  : lookback<C, S, 16>(st, tile, kRadix);
+        status_store(st, St::kInc | static_cast<S>(excl + cnt));
+      }
+      s_doff[tid] = seg_base[(static_cast<size_t>(cur_seg) * P + pass) * kRadix + tid] + excl - start;
+    }
+    lds_barrier();
+
+    const C remaining = cur_end - cur_base;
+    const int valid = remaining < static_cast<C>(kTile) ? static_cast<int>(remaining) : kTile;
+#pragma unroll 4
+    for (int i = tid; i < valid; i += kThreads) {
+      const K k = s_stage[pad16(i)];
+      const C o = s_doff[digit_of(k, shift)] + static_cast<C>(i);
+      dst[o] = k ^ out_flip;
+      if constexpr (VALS) dst_v[o] = s_vstage[pad16(i)];
+    }
+    if (!more) break;
+    tile = next;
+    lds_barrier();  // the stage, s_doff and s_hist are reused by the next tile
+  }
+}
+
+// ---------------------------------------------------------------------------
 // 4. copy n results when the plan asks for it.
 template <typename K, bool VALS>
 __global__ __launch_bounds__(256) void plan_copy_kernel(const SortPlan* __restrict__ plan, uint64_t n) {
@@ -832,6 +1099,89 @@ ms_status dispatch(const void* kin, const uint32_t* vin, void* kout, uint32_t* v
   return run_onesweep<K, VALS, uint32_t, uint32_t>(kin, vin, kout, vout, n, flip, w, L, s);
 }
 
+// ---------------------------------------------------------------------------
+// Segmented digit passes (few long segments).
+struct SegSweepLayout {
+  size_t plan = 0, ctrs = 0, hist = 0, base = 0, tstart = 0, status0 = 0, status1 = 0, alt_k = 0, alt_v = 0,
+         total = 0;
+  size_t ctrs_hist_bytes = 0, status_bytes = 0;
+  uint64_t tiles = 0;  // bound on the tile count: every segment adds at most one partial tile
+  bool big = false;
+};
+
+SegSweepLayout segsweep_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg) {
+  SegSweepLayout L;
+  const int kb = key_bytes(kt);
+  const int P = kb;
+  L.big = n >= (1ull << 30);
+  const size_t cb = L.big ? 8 : 4;
+  L.tiles = (n + SegSweepCfg::kTile - 1) / SegSweepCfg::kTile + nseg;
+  size_t off = 0;
+  L.plan = off;
+  off += align_up(sizeof(SortPlan));
+  L.ctrs = off;  // counters and histograms are cleared together
+  off += align_up((1 + kMaxPasses) * sizeof(uint32_t));
+  L.hist = off;
+  off += align_up(nseg * P * kRadix * cb);
+  L.ctrs_hist_bytes = off - L.ctrs;
+  L.base = off;
+  off += align_up(nseg * P * kRadix * cb);
+  L.tstart = off;
+  off += align_up((nseg + 1) * sizeof(uint32_t));
+  L.status_bytes = align_up(static_cast<size_t>(L.tiles) * kRadix * cb);
+  L.status0 = off;
+  off += L.status_bytes;
+  L.status1 = off;
+  off += L.status_bytes;
+  L.alt_k = off;
+  off += align_up(n * kb);
+  if (has_vals) {
+    L.alt_v = off;
+    off += align_up(n * sizeof(uint32_t));
+  }
+  L.total = off;
+  return L;
+}
+
+template <typename K, bool VALS, typename C, typename S>
+ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
+                       uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
+  constexpr int P = sizeof(K);
+  SortPlan* plan = reinterpret_cast<SortPlan*>(ws + L.plan);
+  uint32_t* ctrs = reinterpret_cast<uint32_t*>(ws + L.ctrs);
+  C* hist = reinterpret_cast<C*>(ws + L.hist);
+  C* base = reinterpret_cast<C*>(ws + L.base);
+  uint32_t* tstart = reinterpret_cast<uint32_t*>(ws + L.tstart);
+  S* status[2] = {reinterpret_cast<S*>(ws + L.status0), reinterpret_cast<S*>(ws + L.status1)};
+
+  MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), L.ctrs_hist_bytes / 16,
+            reinterpret_cast<uint4*>(ws + L.status0), L.status_bytes / 16);
+  Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
+  MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, 1024, s, off, nseg, tstart, plan, buf);
+  const uint64_t hblocks = std::min<uint64_t>(L.tiles, 2 * device_cus(256));
+  MS_LAUNCH("segsweep_hist", (segsweep_hist_kernel<K, C>), static_cast<uint32_t>(hblocks), 256, s,
+            static_cast<const K*>(kin), flip, off, nseg, static_cast<const uint32_t*>(tstart), hist);
+  MS_LAUNCH("segsweep_base", segsweep_base_kernel<C>, nseg * P, 256, s, off, P, static_cast<const C*>(hist), base);
+  const uint64_t blocks = std::min<uint64_t>(
+      L.tiles, resident_blocks(reinterpret_cast<const void*>(&segsweep_pass_kernel<K, VALS, C, S>),
+                               kSegSweepThreads, 256));
+  for (int p = 0; p < P; ++p) {
+    S* next = p + 1 < P ? status[(p + 1) & 1] : nullptr;
+    MS_LAUNCH("segsweep_pass", (segsweep_pass_kernel<K, VALS, C, S>), static_cast<uint32_t>(blocks),
+              kSegSweepThreads, s, static_cast<const SortPlan*>(plan), p, off, nseg,
+              static_cast<const uint32_t*>(tstart), flip, static_cast<const C*>(base), ctrs + 1 + p, status[p & 1],
+              next);
+  }
+  return MS_OK;
+}
+
+template <typename K, bool VALS>
+ms_status segsweep_dispatch(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
+                            uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
+  if (L.big) return run_segsweep<K, VALS, uint64_t, uint64_t>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+  return run_segsweep<K, VALS, uint32_t, uint32_t>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+}
+
 }  // namespace
 
 size_t radix_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n) {
@@ -857,6 +1207,38 @@ ms_status radix_sort(const void* keys_in, const uint32_t* vals_in, void* keys_ou
                   : dispatch<uint64_t, false>(keys_in, vals_in, keys_out, vals_out, n, 0ull, ws, L, s);
   }
   return fail(MS_ENOTSUP, "unknown key type %d", static_cast<int>(kt));
+}
+
+bool segsweep_eligible(uint64_t n, uint64_t nseg) {
+  return nseg >= 1 && nseg <= kSegSweepMaxSegments && n > kSegSweepMinAverage * nseg;
+}
+
+size_t segsweep_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg) {
+  return segsweep_layout(kt, has_vals, n, nseg).total;
+}
+
+ms_status segsweep_sort(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
+                        const uint64_t* offsets, uint64_t nseg, uint64_t n, ms_key_type kt, void* ws,
+                        size_t ws_bytes, hipStream_t s) {
+  if (!segsweep_eligible(n, nseg)) return fail(MS_EINVAL, "sort_segmented: internal: segment passes not eligible");
+  const bool vals = vals_in != nullptr;
+  const SegSweepLayout L = segsweep_layout(kt, vals, n, nseg);
+  if (ws_bytes < L.total || !ws)
+    return fail(MS_EINVAL, "sort_segmented: workspace too small: %zu bytes given, %zu needed", ws_bytes, L.total);
+  char* w = static_cast<char*>(ws);
+  const uint32_t ns = static_cast<uint32_t>(nseg);
+  switch (kt) {
+    case MS_KEY_I32:
+      return vals ? segsweep_dispatch<uint32_t, true>(keys_in, vals_in, keys_out, vals_out, offsets, ns, n, 0x80000000u, w, L, s)
+                  : segsweep_dispatch<uint32_t, false>(keys_in, vals_in, keys_out, vals_out, offsets, ns, n, 0x80000000u, w, L, s);
+    case MS_KEY_U32:
+      return vals ? segsweep_dispatch<uint32_t, true>(keys_in, vals_in, keys_out, vals_out, offsets, ns, n, 0u, w, L, s)
+                  : segsweep_dispatch<uint32_t, false>(keys_in, vals_in, keys_out, vals_out, offsets, ns, n, 0u, w, L, s);
+    case MS_KEY_U64:
+      return vals ? segsweep_dispatch<uint64_t, true>(keys_in, vals_in, keys_out, vals_out, offsets, ns, n, 0ull, w, L, s)
+                  : segsweep_dispatch<uint64_t, false>(keys_in, vals_in, keys_out, vals_out, offsets, ns, n, 0ull, w, L, s);
+  }
+  return fail(MS_ENOTSUP, "sort_segmented: unknown key type %d", static_cast<int>(kt));
 }
 
 }  // namespace ms

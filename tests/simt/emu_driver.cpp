@@ -133,6 +133,10 @@ int main(int argc, char** argv) {
     run_sort<uint32_t>(MS_KEY_I32, 120000, "uniform", false, false, 1024);
     run_sort<uint32_t>(MS_KEY_U32, 70001, "small", false, true, 1024);
     run_segmented<uint32_t>(MS_KEY_I32, {0, 5, 9000, 1, 300, 1000, 64, 2, 900, 17, 18, 19, 20}, true);
+    // A few long segments: whole-device digit passes (empty, one-key and
+    // partial-tile segments among them)
+    run_segmented<uint32_t>(MS_KEY_I32, {40000, 0, 20000, 1, 50000}, false, "uniform");
+    run_segmented<uint64_t>(MS_KEY_U64, {70000, 30001}, true, "few");
     run_merge<uint32_t>(MS_KEY_U32, {3000, 0, 2500, 1});
   }
   if (what == "all" || what == "sort") {
@@ -152,6 +156,12 @@ int main(int argc, char** argv) {
   if (what == "low12") {
     run_segmented<uint32_t>(MS_KEY_U32, {18599, 3000, 1200, 40000}, true, "low12");
     run_sort<uint32_t>(MS_KEY_U32, 18599, "low12", true, false, 1024);
+  }
+  if (what == "segsweep") {
+    run_segmented<uint32_t>(MS_KEY_I32, {40000, 0, 20000, 1, 50000}, false, "uniform");
+    run_segmented<uint32_t>(MS_KEY_U32, {16384, 16383, 16385, 8191, 8193}, true, "small");
+    run_segmented<uint64_t>(MS_KEY_U64, {70000, 30001}, true, "few");
+    run_segmented<uint32_t>(MS_KEY_I32, {100000}, true, "sorted");
   }
   if (what == "all" || what == "segmented" || what == "seg") {
     run_segmented<uint32_t>(MS_KEY_I32, {0, 5, 9000, 1, 0, 8192, 8193, 300}, false);

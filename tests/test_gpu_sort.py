@@ -172,6 +172,49 @@ def test_sort_segmented_parity(dt):
             assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (dt, trial, dist)
 
 
+LONG_SEGMENT_CASES = [
+    [40000, 0, 20000, 1, 50000],                 # empty, one-key and partial-tile segments
+    [16384, 16383, 16385, 8191, 8193, 8192, 200000],  # around the 8,192-key tile
+    [(1 << 20) + 3, 1 << 19, 17, 0, 70000],
+    [300000],                                    # one segment: the whole list
+    [25000] * 4,                                 # the paper's 10^5-key, p = 4 parts
+]
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_sort_segmented_long_segments(dt):
+    """At most 1,024 segments averaging >= 16,384 keys take whole-device digit
+    passes (tiles cut from each segment's start, per-segment digit bases, a
+    look-back that ends at the segment's first tile).  Keys and pairs against
+    the oracle, also through a view one key into the buffer (unaligned
+    tiles)."""
+    for ci, lengths in enumerate(LONG_SEGMENT_CASES):
+        off = inputs.offsets_from_lengths(np.array(lengths))
+        n = int(off[-1])
+        for dist in ("uniform", "few", "sorted"):
+            say(f"long segments {dt} case={ci} n={n} nseg={len(lengths)} {dist}")
+            k = inputs.keys(dt, n, dist, seed=ci)
+            v = np.arange(n, dtype=np.uint32)
+            assert np.array_equal(host(api.sort_segmented(dev(k), dev(off))), oracle.sort_segmented(k, off)), \
+                (dt, ci, dist)
+            ko, vo = api.sort_segmented(dev(k), dev(off), dev(v))
+            ek, ev = oracle.sort_segmented(k, off, v)
+            assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (dt, ci, dist)
+        buf = dev(np.concatenate([k[:1], k]))
+        assert np.array_equal(host(api.sort_segmented(buf[1:], dev(off))), oracle.sort_segmented(k, off)), (dt, ci)
+
+
+def test_sort_segmented_long_in_place():
+    lengths = [70000, 1, 33000]
+    off = inputs.offsets_from_lengths(np.array(lengths))
+    k = inputs.keys("i32", int(off[-1]), "uniform", seed=3)
+    v = np.arange(k.size, dtype=np.uint32)
+    tk, tv = dev(k), dev(v)
+    api.sort_segmented(tk, dev(off), tv, keys_out=tk, vals_out=tv)
+    ek, ev = oracle.sort_segmented(k, off, v)
+    assert np.array_equal(host(tk), ek) and np.array_equal(host(tv), ev)
+
+
 def test_sort_segmented_in_place_and_edges():
     k = inputs.keys("i32", 50_000, "uniform", seed=5)
     off = np.array([0, 0, 10, 10, 20_000, 20_001, 50_000, 50_000], dtype=np.uint64)
