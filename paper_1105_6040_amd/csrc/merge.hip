@@ -9,24 +9,31 @@
 // groups of 2^r input runs pairwise, (group 2j, group 2j+1), and copies an
 // unpaired last group.
 //
-// Each thread produces kItems consecutive outputs.  It finds the pair that
-// holds its first output, then the merge-path co-rank of that output's
-// diagonal (how many of the first d outputs come from the left run) by
-// binary search, and merges sequentially from there, crossing into the next
-// pair if its outputs span a pair boundary.  Outputs are staged in LDS and
-// written with coalesced stores.
+// A workgroup produces one tile of kTile consecutive outputs.  When the tile
+// lies inside one pair (the usual case once runs are longer than a tile), one
+// wave finds the merge-path co-rank of each end of the tile (how many of the
+// pair's first d outputs come from the left run) by a 64-way search, the
+// tile's slices of both runs are loaded into LDS with coalesced reads, every
+// thread co-ranks its kItems outputs inside LDS and merges them, and the tile
+// is written back with coalesced stores.  Otherwise every thread finds the
+// pair and co-rank of its first output itself and merges from global memory,
+// crossing into the next pair if its outputs span a pair boundary.
 #include "ms_device.hpp"
 #include "ms_runtime.hpp"
 
 namespace ms {
 namespace {
 
-template <typename K>
+// Tiles of 256 threads x kItems outputs: BIG tiles (16 32-bit or 8 64-bit
+// keys per thread) for long lists, half that below kBigTileMin keys, where
+// more, shorter tiles keep more of the device busy.
+template <typename K, bool BIG>
 struct MergeCfg {
   static constexpr int kThreads = 256;
-  static constexpr int kItems = sizeof(K) == 4 ? 8 : 4;
+  static constexpr int kItems = (sizeof(K) == 4 ? 16 : 8) / (BIG ? 1 : 2);
   static constexpr int kTile = kThreads * kItems;
 };
+constexpr uint64_t kBigTileMin = 1ull << 22;
 
 __device__ __forceinline__ uint64_t clamp_off(const uint64_t* off, uint64_t idx, uint64_t n) {
   const uint64_t v = off[idx];
@@ -41,22 +48,154 @@ __device__ __forceinline__ uint64_t group_begin(const uint64_t* off, uint64_t nr
   return clamp_off(off, idx, n);
 }
 
-template <typename K, bool VALS>
-__global__ __launch_bounds__(MergeCfg<K>::kThreads) void merge_round_kernel(
+// Merge-path co-rank of diagonal d of the pair (A = src[a0, a0 + la),
+// B = src[a1, a1 + lb)): the number i of A items among the first d outputs,
+// i.e. the count of m in [max(0, d - lb), min(d, la)) with A[m] <= B[d-1-m]
+// (true below i, false from i on).  One wave probes 64 evenly spaced m per
+// round, so the range shrinks 64-fold per memory round trip.  All lanes of
+// the wave call it and get the result.
+template <typename K>
+__device__ __forceinline__ uint64_t corank_wave(const K* __restrict__ src, uint64_t a0, uint64_t a1, uint64_t la,
+                                                uint64_t lb, uint64_t d, K flip) {
+  uint64_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;  // the answer lies in [lo, hi]
+  const uint64_t lane = lane_id();
+  while (hi > lo) {
+    const uint64_t step = (hi - lo + kWave - 1) / kWave;
+    const uint64_t m = lo + lane * step;
+    bool le = false;
+    if (m < hi) le = flip_key(src[a0 + m], flip) <= flip_key(src[a1 + (d - 1 - m)], flip);
+    const uint32_t t = static_cast<uint32_t>(__popcll(__builtin_amdgcn_ballot_w64(le)));  // probes 0..t-1 hold
+    if (step == 1) return lo + t;  // every candidate probed
+    if (t == 0) return lo;
+    const uint64_t first_false = lo + t * step;
+    lo = lo + (t - 1) * step + 1;
+    if (first_false < hi) hi = first_false;
+  }
+  return lo;
+}
+
+template <typename K, bool VALS, bool BIG>
+__global__ __launch_bounds__(256) void merge_round_kernel(
     const K* __restrict__ src, const uint32_t* __restrict__ srcv, K* __restrict__ dst, uint32_t* __restrict__ dstv,
     const uint64_t* __restrict__ off, uint64_t nruns, uint64_t n, uint64_t width, K flip) {
-  constexpr int kThreads = MergeCfg<K>::kThreads;
-  constexpr int kItems = MergeCfg<K>::kItems;
-  constexpr int kTile = MergeCfg<K>::kTile;
+  constexpr int kThreads = MergeCfg<K, BIG>::kThreads;
+  static_assert(kThreads == 256, "the launch bound");
+  constexpr int kItems = MergeCfg<K, BIG>::kItems;
+  constexpr int kTile = MergeCfg<K, BIG>::kTile;
   __shared__ K s_out[kTile];
   __shared__ uint32_t s_outv[VALS ? kTile : 1];
 
+  __shared__ uint64_t s_pair[3];  // a0, a1, b1 of the pair holding the whole tile; a0 = ~0: none
+  __shared__ uint64_t s_rank[2];
+
   const int tid = threadIdx.x;
   const uint64_t tile_begin = static_cast<uint64_t>(blockIdx.x) * kTile;
-  uint64_t p = tile_begin + static_cast<uint64_t>(tid) * kItems;
+  const uint64_t tile_end = tile_begin + kTile < n ? tile_begin + kTile : n;
   const uint64_t ngroups = (nruns + width - 1) / width;
   const uint64_t npairs = (ngroups + 1) / 2;
 
+  if (tid == 0) {
+    uint64_t lo = 0, hi = npairs;  // last pair whose start is <= tile_begin
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) / 2;
+      if (group_begin(off, nruns, width, 2 * mid, n) <= tile_begin)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    uint64_t a0 = group_begin(off, nruns, width, 2 * lo, n);
+    uint64_t a1 = group_begin(off, nruns, width, 2 * lo + 1, n);
+    uint64_t b1 = (lo + 1 == npairs) ? n : group_begin(off, nruns, width, 2 * lo + 2, n);
+    if (a1 < a0) a1 = a0;
+    if (b1 < a1) b1 = a1;
+    const bool inside = a0 <= tile_begin && tile_end <= b1;
+    s_pair[0] = inside ? a0 : ~0ull;
+    s_pair[1] = a1;
+    s_pair[2] = b1;
+  }
+  __syncthreads();
+  if (s_pair[0] != ~0ull) {
+    const uint64_t a0 = s_pair[0], a1 = s_pair[1], b1 = s_pair[2];
+    const uint64_t la = a1 - a0, lb = b1 - a1;
+    const uint64_t d0 = tile_begin - a0, d1 = tile_end - a0;
+    const int wave = tid / kWave;
+    if (wave < 2) {
+      const uint64_t r = corank_wave<K>(src, a0, a1, la, lb, wave == 0 ? d0 : d1, flip);
+      if (lane_id() == 0) s_rank[wave] = r;
+    }
+    __syncthreads();
+    const uint64_t i0 = s_rank[0], i1 = s_rank[1];
+    const int na = static_cast<int>(i1 - i0);               // A items of the tile
+    const int total = static_cast<int>(tile_end - tile_begin);
+    const int nb = total - na;
+    const uint64_t b0 = a1 + (d0 - i0);                     // first B item of the tile
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {  // all loads in flight at once
+      const int e = q * kThreads + tid;
+      if (e < total) {
+        const uint64_t from = e < na ? a0 + i0 + e : b0 + (e - na);
+        s_out[e] = src[from];
+        if constexpr (VALS) s_outv[e] = srcv[from];
+      }
+    }
+    __syncthreads();
+    // This thread's outputs: tile positions [dd, dd + kItems) of A' = s_out[0, na)
+    // and B' = s_out[na, total).
+    const int dd = tid * kItems;
+    K ok[kItems];
+    uint32_t ov[kItems];
+    int cnt = 0;
+    if (dd < total) {
+      int lo = dd > nb ? dd - nb : 0, hi = dd < na ? dd : na;
+      while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (flip_key(s_out[mid], flip) <= flip_key(s_out[na + dd - 1 - mid], flip))
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      int i = lo, k = dd - lo;
+      cnt = total - dd < kItems ? total - dd : kItems;
+      // The heads of both runs stay in registers: one LDS read per output
+      // (an index past its run reads a neighbour that is never taken).
+      K ha = s_out[i < kTile ? i : kTile - 1];
+      K hb = s_out[na + k < kTile ? na + k : kTile - 1];
+#pragma unroll
+      for (int q = 0; q < kItems; ++q) {
+        if (q < cnt) {
+          const bool take_a = k >= nb || (i < na && flip_key(ha, flip) <= flip_key(hb, flip));
+          ok[q] = take_a ? ha : hb;
+          if constexpr (VALS) ov[q] = s_outv[take_a ? i : na + k];
+          i += take_a;
+          k += !take_a;
+          const int nxt = take_a ? i : na + k;
+          const K h = s_out[nxt < kTile ? nxt : kTile - 1];
+          ha = take_a ? h : ha;
+          hb = take_a ? hb : h;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+      if (q < cnt) {
+        s_out[dd + q] = ok[q];
+        if constexpr (VALS) s_outv[dd + q] = ov[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+      const int e = q * kThreads + tid;
+      if (e < total) {
+        dst[tile_begin + e] = s_out[e];
+        if constexpr (VALS) dstv[tile_begin + e] = s_outv[e];
+      }
+    }
+    return;
+  }
+
+  uint64_t p = tile_begin + static_cast<uint64_t>(tid) * kItems;
   int produced = 0;
   while (produced < kItems && p < n) {
     // Last pair whose start is <= p (pair starts are non-decreasing).
@@ -168,14 +307,20 @@ ms_status run_merge(const void* kin, const uint32_t* vin, void* kout, uint32_t* 
   uint32_t* alt_v = (VALS && L.rounds >= 2) ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr;
   const K* src = static_cast<const K*>(kin);
   const uint32_t* srcv = vin;
-  const uint64_t blocks = (n + MergeCfg<K>::kTile - 1) / MergeCfg<K>::kTile;
+  const bool big = n >= kBigTileMin;
+  const uint64_t tile = big ? MergeCfg<K, true>::kTile : MergeCfg<K, false>::kTile;
+  const uint64_t blocks = (n + tile - 1) / tile;
   if (blocks > 0x7fffffffull) return fail(MS_ENOTSUP, "merge_runs: list too long");
   for (int r = 0; r < L.rounds; ++r) {
     const bool to_out = ((L.rounds - 1 - r) % 2) == 0;
     K* dst = to_out ? static_cast<K*>(kout) : alt_k;
     uint32_t* dstv = to_out ? vout : alt_v;
-    MS_LAUNCH("merge_round", (merge_round_kernel<K, VALS>), static_cast<uint32_t>(blocks), MergeCfg<K>::kThreads, s,
-              src, srcv, dst, dstv, off, nruns, n, 1ull << r, flip);
+    if (big)
+      MS_LAUNCH("merge_round", (merge_round_kernel<K, VALS, true>), static_cast<uint32_t>(blocks), 256, s, src, srcv,
+                dst, dstv, off, nruns, n, 1ull << r, flip);
+    else
+      MS_LAUNCH("merge_round", (merge_round_kernel<K, VALS, false>), static_cast<uint32_t>(blocks), 256, s, src,
+                srcv, dst, dstv, off, nruns, n, 1ull << r, flip);
     src = dst;
     srcv = dstv;
   }

@@ -138,6 +138,7 @@ int main(int argc, char** argv) {
     run_segmented<uint32_t>(MS_KEY_I32, {40000, 0, 20000, 1, 50000}, false, "uniform");
     run_segmented<uint64_t>(MS_KEY_U64, {70000, 30001}, true, "few");
     run_merge<uint32_t>(MS_KEY_U32, {3000, 0, 2500, 1});
+    run_merge<uint32_t>(MS_KEY_I32, {20000, 30000, 5, 70000});
   }
   if (what == "all" || what == "sort") {
     for (int threads : {256, 512, 1024}) {
@@ -174,6 +175,9 @@ int main(int argc, char** argv) {
   if (what == "all" || what == "merge") {
     run_merge<uint32_t>(MS_KEY_I32, {3000, 0, 2500, 4000, 1});
     run_merge<uint64_t>(MS_KEY_U64, {1000, 2000});
+    // runs of several tiles: most tiles lie inside one pair
+    run_merge<uint32_t>(MS_KEY_U32, {20000, 30000, 5, 70000});
+    run_merge<uint64_t>(MS_KEY_U64, {9000, 9001, 4095});
   }
   printf("%d failure(s)\n", failures);
   return failures ? 1 : 0;

@@ -244,6 +244,26 @@ def test_merge_runs_parity(dt, nruns):
         assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (dt, nruns, trial)
 
 
+@pytest.mark.parametrize("dt", DTYPES)
+def test_merge_runs_long_runs(dt):
+    """Runs of hundreds of merge tiles (most tiles inside one pair: 64-way
+    co-rank search, LDS merge), tie-heavy keys for the left-first rule, and a
+    view one key into the buffer."""
+    lengths = [1 << 20, (1 << 20) + 3, 77, 0, 300001]
+    off = inputs.offsets_from_lengths(np.array(lengths))
+    n = int(off[-1])
+    for dist in ("few", "uniform"):
+        say(f"merge_runs long {dt} n={n} {dist}")
+        k = inputs.keys(dt, n, dist, seed=len(dist))
+        v = np.arange(n, dtype=np.uint32)
+        rk, rv = oracle.sort_segmented(k, off, v)  # sorted runs (input construction)
+        ek, ev = oracle.merge_runs(rk, off, rv)
+        ko, vo = api.merge_runs(dev(rk), dev(off), dev(rv))
+        assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (dt, dist)
+        buf = dev(np.concatenate([rk[:1], rk]))
+        assert np.array_equal(host(api.merge_runs(buf[1:], dev(off))), ek), (dt, dist)
+
+
 def test_paper_method_small():
     """100,000 int32 keys, p = 4 equal parts: sort each part, merge (Figure 1)."""
     k, p = inputs.paper_small(0)
