@@ -18,6 +18,7 @@ JSON line:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu] [--no-tune]
        python bench.py --psweep    (the process-count sweep instead of the headline)
+       python bench.py --memory    (device bytes against list size; no GPU needed)
 
 --no-tune runs the library's default launch parameters instead of timing
 candidates first (profiling runs use it, so that only the measured kernels
@@ -116,11 +117,17 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--psweep", action="store_true",
                     help="instead of the headline: the process-count sweep (paper's method, p = 1..64)")
+    ap.add_argument("--memory", action="store_true",
+                    help="instead of the headline: device bytes against list size (no GPU needed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (no multi-GPU path is built)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.memory:
+        print(json.dumps(memory_table()), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -267,6 +274,34 @@ def extra_workloads(args, dev, stream, keys_u, keys_u_np):
     ex["segments_50k"] = segments_workload(dev, stream)
     ex["serving"] = serving_workload(dev)
     return ex
+
+
+def memory_table():
+    """The paper's Experiment 2 on the GPU: device bytes the sort takes as the
+    list grows, with two parts (its two processes).  Per call: the keys in,
+    the keys out and the workspace the library asks for (ms_workspace_size);
+    the paper's method (two parts sorted, then merged) also holds the sorted
+    parts between its two calls.  Table 2's list sizes: 5..10 x 10^4 and
+    2.5..5 x 10^6 int32 keys."""
+    from paper_1105_6040_amd import _native as N
+
+    K = 4
+    rows = []
+    for n in [k * 10**4 for k in range(5, 11)] + [k * 5 * 10**5 for k in range(5, 11)]:
+        ws_sort = N.workspace_size(N.MS_OP_SORT_KEYS, N.MS_KEY_I32, False, n)
+        ws_seg = N.workspace_size(N.MS_OP_SORT_SEGMENTED, N.MS_KEY_I32, False, n, 2)
+        ws_merge = N.workspace_size(N.MS_OP_MERGE_RUNS, N.MS_KEY_I32, False, n, 2)
+        whole = 2 * n * K + ws_sort
+        method = 3 * n * K + max(ws_seg, ws_merge)  # keys, sorted parts, merged output; one workspace reused
+        rows.append({"n": n, "sort_keys_bytes": whole, "sort_keys_workspace": ws_sort,
+                     "paper_method_p2_bytes": method, "sort_segmented_workspace": ws_seg,
+                     "merge_runs_workspace": ws_merge})
+    big = [r for r in rows if r["n"] >= 2_500_000]
+    slope = lambda key: (big[-1][key] - big[0][key]) / (big[-1]["n"] - big[0]["n"])  # noqa: E731
+    return {"experiment": "device memory against list size (paper's Experiment 2, Table 2 sizes), int32 keys",
+            "unit": "bytes", "rows": rows,
+            "bytes_per_key_2p5e6_to_5e6": {"sort_keys": round(slope("sort_keys_bytes"), 3),
+                                            "paper_method_p2": round(slope("paper_method_p2_bytes"), 3)}}
 
 
 def process_sweep(dev, stream, reps=20, warmup=5):

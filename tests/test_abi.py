@@ -74,3 +74,31 @@ def test_host_side_argument_errors():
     assert lib.merge_runs(fake, None, ctypes.c_void_p(0x2000), None, fake, 0, 5, 0, None, 0, None) == N.MS_EINVAL
     assert lib.merge_runs(fake, None, fake, None, fake, 2, 5, 0, None, 0, None) == N.MS_EINVAL
     assert "alias" in N.last_error()
+
+
+def _align(x, a=256):
+    return (x + a - 1) // a * a
+
+
+def test_sort_keys_workspace_follows_the_layout():
+    """ms_workspace_size for sort_keys of int32 keys is the documented layout:
+    plan (512 B), counters (256 B), digit histograms and bases (2 x 4 x 256 x
+    4 B), two look-back status buffers of ceil(n / 4096) rows of 256 words,
+    and the n-key ping-pong buffer; 1,207,968,512 B at 2^28 keys."""
+    for n in (8193, 100_000, (1 << 20) + 1, 6_000_000, 1 << 28):
+        rows = -(-n // 4096)
+        expect = 512 + 256 + 2 * 4 * 256 * 4 + 2 * _align(rows * 256 * 4) + _align(4 * n)
+        assert N.workspace_size(N.MS_OP_SORT_KEYS, N.MS_KEY_I32, False, n) == expect, n
+    assert N.workspace_size(N.MS_OP_SORT_KEYS, N.MS_KEY_I32, False, 1 << 28) == 1_207_968_512
+
+
+def test_memory_against_list_size():
+    """The memory experiment (bench.py --memory): device bytes grow by 12.5 B
+    per int32 key for sort_keys (in, out, ping-pong, status) over Table 2's
+    2.5..5 x 10^6 range, and stay affine in n."""
+    import bench
+    t = bench.memory_table()
+    assert t["bytes_per_key_2p5e6_to_5e6"]["sort_keys"] == 12.5
+    big = [r for r in t["rows"] if r["n"] >= 2_500_000]
+    steps = {b["sort_keys_bytes"] - a["sort_keys_bytes"] for a, b in zip(big, big[1:])}
+    assert max(steps) - min(steps) <= 2 * 1024 + 256, steps  # status rows and alignment only
