@@ -308,8 +308,10 @@ def process_sweep(dev, stream, reps=20, warmup=5):
     """The paper's Experiment 1 on the GPU: a list of n int32 keys (2*10^5 and
     6*10^6, Table 1's sizes) split into p = 1, 2, 4, ..., 64 contiguous parts,
     each part sorted (sort_segmented, one launch for all parts), then the p
-    sorted parts merged (merge_runs).  Median of `reps` HIP-event-timed runs
-    per phase; every result must equal sort_keys on the whole list."""
+    sorted parts merged (merge_runs: merge-path rounds), and the same merge
+    by Figure 1's odd/even merge-split schedule (merge_split: p phases).
+    Median of `reps` HIP-event-timed runs per phase; every result must equal
+    sort_keys on the whole list."""
     import numpy as np
     import torch
 
@@ -337,10 +339,14 @@ def process_sweep(dev, stream, reps=20, warmup=5):
                     sort_ms.append(ev[0].elapsed_time(ev[1]))
                     merge_ms.append(ev[1].elapsed_time(ev[2]))
             assert torch.equal(m_out, ref), f"paper method differs from sort_keys at n={n}, p={p}"
+            # The same merge phase by Figure 1's own schedule (p merge-split phases).
+            _, split = time_steps(lambda: api.merge_split(s_out, p, keys_out=m_out), reps, warmup, stream)
+            assert torch.equal(m_out, ref), f"merge-split differs from sort_keys at n={n}, p={p}"
             med = lambda xs: sorted(xs)[len(xs) // 2]  # noqa: E731
             rows.append({"n": n, "p": p, "sort_phase_us": round(med(sort_ms) * 1e3, 1),
                          "merge_phase_us": round(med(merge_ms) * 1e3, 1),
                          "total_us": round(med([a + b for a, b in zip(sort_ms, merge_ms)]) * 1e3, 1),
+                         "merge_split_phase_us": round(med(split) * 1e3, 1),
                          "sort_keys_whole_list_us": round(med(whole) * 1e3, 1)})
             log(rows[-1])
         del k, ref, s_out, m_out

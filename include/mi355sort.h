@@ -60,7 +60,8 @@ typedef enum ms_op {
     MS_OP_SORT_KEYS = 0,
     MS_OP_SORT_PAIRS = 1,
     MS_OP_SORT_SEGMENTED = 2,
-    MS_OP_MERGE_RUNS = 3
+    MS_OP_MERGE_RUNS = 3,
+    MS_OP_MERGE_SPLIT = 4
 } ms_op;
 
 /*
@@ -118,6 +119,27 @@ ms_status sort_segmented(const void *keys_in, const uint32_t *vals_in, void *key
 ms_status merge_runs(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
                      const uint64_t *run_offsets, uint64_t num_runs, uint64_t n_total,
                      ms_key_type kt, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The merge phase by Figure 1's own schedule, odd/even transposition
+ * merge-split: the input holds num_parts sorted parts of n_total / num_parts
+ * keys each (part i = [i*s, (i+1)*s)); in phase k = 0 .. num_parts-1 the
+ * parts (0,1), (2,3), ... (k even) or (1,2), (3,4), ... (k odd) are merged
+ * pairwise (the lower part's item first on equal keys) and split by count,
+ * the lower part keeping the first s items; an unpaired part is copied.
+ * After num_parts phases the list is sorted, with the same result as
+ * merge_runs over the same parts (the stable sort of the concatenation), at
+ * num_parts passes over the data instead of ceil(log2(num_parts)).
+ * keys_out must not overlap keys_in (nor vals_out vals_in).  Errors:
+ * MS_EINVAL for NULL pointers with n_total > 0, num_parts = 0, num_parts
+ * not dividing n_total (count-preserving exchanges cannot carry items across
+ * unequal parts), aliasing, only one of vals_in / vals_out, or a workspace
+ * below ms_workspace_size(MS_OP_MERGE_SPLIT, kt, has_values, n_total,
+ * num_parts); MS_ENOTSUP for an unknown key type.
+ */
+ms_status merge_split(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
+                      uint64_t n_total, uint64_t num_parts, ms_key_type kt, void *ws, size_t ws_bytes,
+                      void *stream);
 
 /* Text describing the last non-OK status returned on this host thread
  * ("" if none).  The pointer stays valid until the thread's next call. */

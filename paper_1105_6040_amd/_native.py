@@ -20,9 +20,10 @@ STATUS_NAMES = {0: "MS_OK", 1: "MS_EINVAL", 2: "MS_ENOMEM", 3: "MS_EDEVICE", 4: 
 # ms_key_type
 MS_KEY_I32, MS_KEY_U32, MS_KEY_U64 = 0, 1, 2
 # ms_op
-MS_OP_SORT_KEYS, MS_OP_SORT_PAIRS, MS_OP_SORT_SEGMENTED, MS_OP_MERGE_RUNS = 0, 1, 2, 3
+MS_OP_SORT_KEYS, MS_OP_SORT_PAIRS, MS_OP_SORT_SEGMENTED, MS_OP_MERGE_RUNS, MS_OP_MERGE_SPLIT = 0, 1, 2, 3, 4
 
-EXPORTS = ("ms_workspace_size", "sort_keys", "sort_pairs", "sort_segmented", "merge_runs", "ms_last_error",
+EXPORTS = ("ms_workspace_size", "sort_keys", "sort_pairs", "sort_segmented", "merge_runs", "merge_split",
+           "ms_last_error",
            "ms_timing_enable", "ms_timing_reset", "ms_timing_read", "ms_tune_set", "ms_tune_get")
 # ms_tune_param
 MS_TUNE_PASS_THREADS = 0
@@ -64,7 +65,8 @@ def lib() -> ctypes.CDLL:
         L.sort_pairs.argtypes = [vp, vp, vp, vp, u64, i32, vp, sz, vp]
         L.sort_segmented.argtypes = [vp, vp, vp, vp, vp, u64, u64, i32, vp, sz, vp]
         L.merge_runs.argtypes = [vp, vp, vp, vp, vp, u64, u64, i32, vp, sz, vp]
-        for fn in ("ms_workspace_size", "sort_keys", "sort_pairs", "sort_segmented", "merge_runs",
+        L.merge_split.argtypes = [vp, vp, vp, vp, u64, u64, i32, vp, sz, vp]
+        for fn in ("ms_workspace_size", "sort_keys", "sort_pairs", "sort_segmented", "merge_runs", "merge_split",
                    "ms_timing_enable", "ms_timing_reset"):
             getattr(L, fn).restype = i32
         L.ms_last_error.argtypes = []

@@ -158,3 +158,22 @@ def merge_runs(keys: torch.Tensor, offsets: torch.Tensor, vals: Optional[torch.T
     N.check(N.lib().merge_runs(_ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), _ptr(offsets), nruns, n,
                                kt, _ptr(w), wb, _stream(keys.device)), "merge_runs")
     return keys_out if vals is None else (keys_out, vals_out)
+
+
+def merge_split(keys: torch.Tensor, p: int, vals: Optional[torch.Tensor] = None,
+                keys_out: Optional[torch.Tensor] = None, vals_out: Optional[torch.Tensor] = None,
+                ws: Optional[torch.Tensor] = None):
+    """Merge p equal sorted parts by Figure 1's odd/even merge-split schedule
+    (p phases).  Same result as merge_runs.  Returns keys or (keys, vals)."""
+    _check_1d(keys, "keys")
+    kt = key_type(keys)
+    n = keys.numel()
+    if vals is not None:
+        _check_vals(vals, n)
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    if vals is not None and vals_out is None:
+        vals_out = torch.empty_like(vals)
+    w, wb = workspace(N.MS_OP_MERGE_SPLIT, kt, vals is not None, n, p, keys.device, ws)
+    N.check(N.lib().merge_split(_ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), n, p, kt, _ptr(w), wb,
+                                _stream(keys.device)), "merge_split")
+    return keys_out if vals is None else (keys_out, vals_out)

@@ -98,6 +98,9 @@ ms_status ms_workspace_size(ms_op op, ms_key_type kt, int has_values, uint64_t n
     case MS_OP_MERGE_RUNS:
       *bytes = ms::merge_workspace_bytes(kt, has_values != 0, n_total, num_segments);
       return MS_OK;
+    case MS_OP_MERGE_SPLIT:
+      *bytes = ms::merge_split_workspace_bytes(kt, has_values != 0, n_total, num_segments);
+      return MS_OK;
   }
   return fail(MS_ENOTSUP, "unknown op %d", static_cast<int>(op));
 }
@@ -168,6 +171,26 @@ ms_status merge_runs(const void* keys_in, const uint32_t* vals_in, void* keys_ou
     return fail(MS_EINVAL, "merge_runs: output must not alias the input");
   return ms::merge_sorted_runs(keys_in, vals_in, keys_out, vals_out, run_offsets, num_runs, n_total, kt, ws,
                                ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+ms_status merge_split(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
+                      uint64_t n_total, uint64_t num_parts, ms_key_type kt, void* ws, size_t ws_bytes,
+                      void* stream) {
+  if (!ms::valid_kt(kt)) return fail(MS_ENOTSUP, "merge_split: unknown key type %d", static_cast<int>(kt));
+  if ((vals_in == nullptr) != (vals_out == nullptr))
+    return fail(MS_EINVAL, "merge_split: give both vals_in and vals_out, or neither");
+  if (num_parts == 0) return fail(MS_EINVAL, "merge_split: num_parts must be at least 1");
+  if (n_total % num_parts != 0)
+    return fail(MS_EINVAL, "merge_split: %llu parts do not divide %llu keys into equal parts",
+                static_cast<unsigned long long>(num_parts), static_cast<unsigned long long>(n_total));
+  if (n_total == 0) return MS_OK;
+  if (!keys_in || !keys_out)
+    return fail(MS_EINVAL, "merge_split: NULL key pointer with n_total = %llu",
+                static_cast<unsigned long long>(n_total));
+  if (keys_in == keys_out || (vals_in && static_cast<const void*>(vals_in) == static_cast<const void*>(vals_out)))
+    return fail(MS_EINVAL, "merge_split: output must not alias the input");
+  return ms::merge_split_parts(keys_in, vals_in, keys_out, vals_out, n_total, num_parts, kt, ws, ws_bytes,
+                               static_cast<hipStream_t>(stream));
 }
 
 ms_status ms_tune_set(ms_tune_param p, int64_t value) {

@@ -327,7 +327,113 @@ ms_status run_merge(const void* kin, const uint32_t* vin, void* kout, uint32_t* 
   return MS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Figure 1's merge loop as odd/even transposition merge-split over p equal
+// parts: p phases, each one merge_round_kernel launch of width 1 over the
+// phase's pairs (an odd phase works on the view that starts one part in, and
+// part 0 is copied).  Merging a pair into the same positions and keeping the
+// first s outputs in the lower part is the count-preserving split.
+
+__global__ __launch_bounds__(256) void part_offsets_kernel(uint64_t* off, uint64_t n, uint64_t p) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 256;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x; i <= p; i += stride) off[i] = i * (n / p);
+}
+
+struct SplitLayout {
+  size_t off = 0, alt_k = 0, alt_v = 0, total = 0;
+};
+
+SplitLayout split_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64_t p) {
+  SplitLayout L;
+  if (p < 2 || n == 0) return L;  // one part: a copy
+  size_t o = 0;
+  L.off = o;
+  o += align_up((p + 1) * sizeof(uint64_t));
+  L.alt_k = o;
+  o += align_up(n * key_bytes(kt));
+  if (has_vals) {
+    L.alt_v = o;
+    o += align_up(n * sizeof(uint32_t));
+  }
+  L.total = o;
+  return L;
+}
+
+template <typename K, bool VALS>
+ms_status run_merge_split(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, uint64_t n, uint64_t p,
+                          K flip, char* ws, const SplitLayout& L, hipStream_t s) {
+  uint64_t cblocks = (n + 255) / 256;
+  if (cblocks > 4096) cblocks = 4096;
+  if (p < 2) {
+    MS_LAUNCH("merge_copy", (copy_kernel<K, VALS>), static_cast<uint32_t>(cblocks), 256, s,
+              static_cast<const K*>(kin), vin, static_cast<K*>(kout), vout, n);
+    return MS_OK;
+  }
+  uint64_t* off = reinterpret_cast<uint64_t*>(ws + L.off);
+  K* alt_k = reinterpret_cast<K*>(ws + L.alt_k);
+  uint32_t* alt_v = VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr;
+  MS_LAUNCH("part_offsets", part_offsets_kernel, static_cast<uint32_t>((p + 256) / 256), 256, s, off, n, p);
+  const uint64_t sz = n / p;
+  const bool big = n >= kBigTileMin;
+  const uint64_t tile = big ? MergeCfg<K, true>::kTile : MergeCfg<K, false>::kTile;
+  const K* src = static_cast<const K*>(kin);
+  const uint32_t* srcv = vin;
+  for (uint64_t k = 0; k < p; ++k) {
+    const bool to_out = ((p - 1 - k) % 2) == 0;
+    K* dst = to_out ? static_cast<K*>(kout) : alt_k;
+    uint32_t* dstv = to_out ? vout : alt_v;
+    // Even phase: parts (0,1), (2,3), ... of the whole list.  Odd phase: part
+    // 0 copied, then parts (1,2), (3,4), ... as pairs of the view one part in.
+    const uint64_t skip = (k % 2 == 1) ? sz : 0;
+    if (skip)
+      MS_LAUNCH("merge_copy", (copy_kernel<K, VALS>), static_cast<uint32_t>(cblocks), 256, s, src, srcv, dst, dstv,
+                sz);
+    const uint64_t m = n - skip;
+    const uint64_t blocks = (m + tile - 1) / tile;
+    const K* vs = src + skip;
+    K* vd = dst + skip;
+    const uint32_t* vsv = VALS ? srcv + skip : nullptr;
+    uint32_t* vdv = VALS ? dstv + skip : nullptr;
+    if (big)
+      MS_LAUNCH("merge_split_phase", (merge_round_kernel<K, VALS, true>), static_cast<uint32_t>(blocks), 256, s, vs,
+                vsv, vd, vdv, static_cast<const uint64_t*>(off), p - (skip ? 1 : 0), m, 1ull, flip);
+    else
+      MS_LAUNCH("merge_split_phase", (merge_round_kernel<K, VALS, false>), static_cast<uint32_t>(blocks), 256, s,
+                vs, vsv, vd, vdv, static_cast<const uint64_t*>(off), p - (skip ? 1 : 0), m, 1ull, flip);
+    src = dst;
+    srcv = dstv;
+  }
+  return MS_OK;
+}
+
 }  // namespace
+
+size_t merge_split_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nparts) {
+  return split_layout(kt, has_vals, n, nparts).total;
+}
+
+ms_status merge_split_parts(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
+                            uint64_t n, uint64_t nparts, ms_key_type kt, void* ws, size_t ws_bytes, hipStream_t s) {
+  const bool vals = vals_in != nullptr;
+  const SplitLayout L = split_layout(kt, vals, n, nparts);
+  if (ws_bytes < L.total || (L.total && !ws))
+    return fail(MS_EINVAL, "merge_split: workspace too small: %zu bytes given, %zu needed", ws_bytes, L.total);
+  if ((n + MergeCfg<uint64_t, false>::kTile - 1) / MergeCfg<uint64_t, false>::kTile > 0x7fffffffull)
+    return fail(MS_ENOTSUP, "merge_split: list too long");
+  char* w = static_cast<char*>(ws);
+  switch (kt) {
+    case MS_KEY_I32:
+      return vals ? run_merge_split<uint32_t, true>(keys_in, vals_in, keys_out, vals_out, n, nparts, 0x80000000u, w, L, s)
+                  : run_merge_split<uint32_t, false>(keys_in, vals_in, keys_out, vals_out, n, nparts, 0x80000000u, w, L, s);
+    case MS_KEY_U32:
+      return vals ? run_merge_split<uint32_t, true>(keys_in, vals_in, keys_out, vals_out, n, nparts, 0u, w, L, s)
+                  : run_merge_split<uint32_t, false>(keys_in, vals_in, keys_out, vals_out, n, nparts, 0u, w, L, s);
+    case MS_KEY_U64:
+      return vals ? run_merge_split<uint64_t, true>(keys_in, vals_in, keys_out, vals_out, n, nparts, 0ull, w, L, s)
+                  : run_merge_split<uint64_t, false>(keys_in, vals_in, keys_out, vals_out, n, nparts, 0ull, w, L, s);
+  }
+  return fail(MS_ENOTSUP, "merge_split: unknown key type %d", static_cast<int>(kt));
+}
 
 size_t merge_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nruns) {
   return merge_layout(kt, has_vals, n, nruns).total;

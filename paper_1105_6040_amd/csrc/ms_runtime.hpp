@@ -61,6 +61,9 @@ ms_status segsweep_sort(const void* keys_in, const uint32_t* vals_in, void* keys
 
 // ---- merge of sorted runs ---------------------------------------------------
 size_t merge_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nruns);
+size_t merge_split_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nparts);
+ms_status merge_split_parts(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
+                            uint64_t n, uint64_t nparts, ms_key_type kt, void* ws, size_t ws_bytes, hipStream_t s);
 ms_status merge_sorted_runs(const void* keys_in, const uint32_t* vals_in, void* keys_out,
                             uint32_t* vals_out, const uint64_t* offsets, uint64_t nruns, uint64_t n,
                             ms_key_type kt, void* ws, size_t ws_bytes, hipStream_t s);

@@ -16,6 +16,8 @@ int oracle_sort_segmented(int kt, const void* kin, const uint32_t* vin, void* ko
                           const uint64_t* off, uint64_t nseg);
 int oracle_merge_runs(int kt, const void* kin, const uint32_t* vin, void* kout, uint32_t* vout,
                       const uint64_t* off, uint64_t nruns);
+int oracle_merge_split(int kt, const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, uint64_t n,
+                       uint64_t p);
 }
 
 static uint64_t g_state = 0x9e3779b97f4a7c15ull;
@@ -99,6 +101,30 @@ static void run_segmented(int kt, const std::vector<uint64_t>& lengths, bool pai
 }
 
 template <typename K>
+static void run_merge_split(int kt, size_t n, uint64_t p, bool pairs, const char* dist) {
+  std::vector<uint64_t> bits;
+  fill(bits, kt, n, dist);
+  std::vector<K> raw = narrow<K>(bits), kin(n), kout(n), kexp(n);
+  std::vector<uint32_t> vraw(n), vin(n), vout(n), vexp(n);
+  for (size_t i = 0; i < n; ++i) vraw[i] = static_cast<uint32_t>(i);
+  std::vector<uint64_t> off(p + 1);
+  for (uint64_t i = 0; i <= p; ++i) off[i] = i * (n / p);
+  oracle_sort_segmented(kt, raw.data(), vraw.data(), kin.data(), vin.data(), off.data(), p);  // sorted parts
+  oracle_merge_split(kt, raw.data(), pairs ? vraw.data() : nullptr, kexp.data(), pairs ? vexp.data() : nullptr, n, p);
+  size_t wsb = 0;
+  ms_workspace_size(MS_OP_MERGE_SPLIT, (ms_key_type)kt, pairs, n, p, &wsb);
+  std::vector<char> ws(wsb + 1);
+  ms_status st = merge_split(kin.data(), pairs ? vin.data() : nullptr, kout.data(), pairs ? vout.data() : nullptr, n, p,
+                             (ms_key_type)kt, ws.data(), wsb, nullptr);
+  bool ok = st == MS_OK && memcmp(kout.data(), kexp.data(), n * sizeof(K)) == 0 &&
+            (!pairs || memcmp(vout.data(), vexp.data(), n * 4) == 0);
+  printf("%s merge_split kt=%d n=%zu p=%llu pairs=%d dist=%s\n", ok ? "ok  " : "FAIL", kt, n,
+         static_cast<unsigned long long>(p), pairs, dist);
+  fflush(stdout);
+  if (!ok) ++failures;
+}
+
+template <typename K>
 static void run_merge(int kt, const std::vector<uint64_t>& lengths) {
   std::vector<uint64_t> off(lengths.size() + 1, 0);
   for (size_t s = 0; s < lengths.size(); ++s) off[s + 1] = off[s] + lengths[s];
@@ -139,6 +165,7 @@ int main(int argc, char** argv) {
     run_segmented<uint64_t>(MS_KEY_U64, {70000, 30001}, true, "few");
     run_merge<uint32_t>(MS_KEY_U32, {3000, 0, 2500, 1});
     run_merge<uint32_t>(MS_KEY_I32, {20000, 30000, 5, 70000});
+    run_merge_split<uint32_t>(MS_KEY_I32, 5 * 4001, 5, true, "few");
   }
   if (what == "all" || what == "sort") {
     for (int threads : {256, 512, 1024}) {
@@ -178,6 +205,9 @@ int main(int argc, char** argv) {
     // runs of several tiles: most tiles lie inside one pair
     run_merge<uint32_t>(MS_KEY_U32, {20000, 30000, 5, 70000});
     run_merge<uint64_t>(MS_KEY_U64, {9000, 9001, 4095});
+    for (uint64_t p : {1, 2, 3, 4, 7})
+      run_merge_split<uint32_t>(MS_KEY_U32, p * 3001, p, p % 2 == 1, "small");
+    run_merge_split<uint64_t>(MS_KEY_U64, 4 * 5000, 4, true, "few");
   }
   printf("%d failure(s)\n", failures);
   return failures ? 1 : 0;

@@ -21,7 +21,8 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for fn in ("sort_keys", "sort_pairs", "sort_segmented", "merge_runs", "ms_workspace_size", "ms_last_error"):
+    for fn in ("sort_keys", "sort_pairs", "sort_segmented", "merge_runs", "merge_split", "ms_workspace_size",
+               "ms_last_error"):
         assert fn in names
 
 
@@ -102,3 +103,21 @@ def test_memory_against_list_size():
     big = [r for r in t["rows"] if r["n"] >= 2_500_000]
     steps = {b["sort_keys_bytes"] - a["sort_keys_bytes"] for a, b in zip(big, big[1:])}
     assert max(steps) - min(steps) <= 2 * 1024 + 256, steps  # status rows and alignment only
+
+
+def test_merge_split_host_side_errors():
+    """Figure 1's schedule needs p equal parts: checked on the host."""
+    lib = N.lib()
+    a, b = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    assert lib.merge_split(a, None, b, None, 0, 3, N.MS_KEY_I32, None, 0, None) == N.MS_OK   # empty list
+    assert lib.merge_split(a, None, b, None, 10, 0, N.MS_KEY_I32, None, 0, None) == N.MS_EINVAL
+    assert lib.merge_split(a, None, b, None, 10, 3, N.MS_KEY_I32, None, 0, None) == N.MS_EINVAL
+    assert "equal parts" in N.last_error()
+    assert lib.merge_split(a, None, a, None, 12, 3, N.MS_KEY_I32, None, 0, None) == N.MS_EINVAL    # aliasing
+    assert lib.merge_split(a, a, b, None, 12, 3, N.MS_KEY_I32, None, 0, None) == N.MS_EINVAL       # one of the values
+    assert lib.merge_split(a, None, b, None, 12, 3, 9, None, 0, None) == N.MS_ENOTSUP
+    assert lib.merge_split(a, None, b, None, 12 * 10**5, 3, N.MS_KEY_I32, None, 0, None) == N.MS_EINVAL
+    assert "workspace" in N.last_error()
+    ws = N.workspace_size
+    assert ws(N.MS_OP_MERGE_SPLIT, N.MS_KEY_I32, False, 1000, 1) == 0      # one part: a copy
+    assert ws(N.MS_OP_MERGE_SPLIT, N.MS_KEY_U64, True, 1000, 4) >= 1000 * 12

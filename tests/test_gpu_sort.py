@@ -264,6 +264,28 @@ def test_merge_runs_long_runs(dt):
         assert np.array_equal(host(api.merge_runs(buf[1:], dev(off))), ek), (dt, dist)
 
 
+@pytest.mark.parametrize("dt", DTYPES)
+def test_merge_split_parity(dt):
+    """Figure 1's odd/even merge-split schedule (p phases over p equal sorted
+    parts) against the oracle's merge-split of the same list, and equal to
+    merge_runs over the same parts (reading 5: every schedule gives the
+    stable sort)."""
+    for p in (1, 2, 3, 4, 5, 8, 16, 64):
+        for s_len in (1000, 4097):
+            n = p * s_len
+            for dist in ("uniform", "few"):
+                say(f"merge_split {dt} p={p} s={s_len} {dist}")
+                k = inputs.keys(dt, n, dist, seed=p + s_len)
+                v = np.arange(n, dtype=np.uint32)
+                off = oracle.part_offsets(n, p)
+                rk, rv = oracle.sort_segmented(k, off, v)  # sorted parts (input construction)
+                ek, ev = oracle.merge_split(k, p, v)
+                ko, vo = api.merge_split(dev(rk), p, dev(rv))
+                assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (dt, p, s_len, dist)
+                mk = api.merge_runs(dev(rk), dev(off))
+                assert np.array_equal(host(api.merge_split(dev(rk), p)), host(mk)), (dt, p, s_len, dist)
+
+
 def test_paper_method_small():
     """100,000 int32 keys, p = 4 equal parts: sort each part, merge (Figure 1)."""
     k, p = inputs.paper_small(0)
