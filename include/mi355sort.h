@@ -158,6 +158,11 @@ const char *ms_last_error(void);
  *   MS_TUNE_HIST_BLOCKS   workgroups of the digit-histogram read of sort_keys /
  *                         sort_pairs (1 .. 65536; 0 = the default, one per
  *                         compute unit).
+ *   MS_TUNE_SMALL_SORT    longest segment of sort_segmented ordered by a
+ *                         comparison network (a bitonic network over one
+ *                         wave, ties ordered by input position, so still the
+ *                         stable sort) instead of radix passes: 64 (the
+ *                         default) or 0 (radix passes for every segment).
  * ms_tune_set returns MS_EINVAL for an unknown parameter or value;
  * ms_tune_get returns the current value (0 for an unknown parameter).
  */
@@ -165,7 +170,8 @@ typedef enum ms_tune_param {
     MS_TUNE_PASS_THREADS = 0,
     MS_TUNE_SEG_BLOCKS = 1,
     MS_TUNE_HIST_BLOCKS = 2,
-    MS_TUNE_COUNT = 3
+    MS_TUNE_SMALL_SORT = 3,
+    MS_TUNE_COUNT = 4
 } ms_tune_param;
 
 ms_status ms_tune_set(ms_tune_param param, int64_t value);

@@ -29,6 +29,7 @@ EXPORTS = ("ms_workspace_size", "sort_keys", "sort_pairs", "sort_segmented", "me
 MS_TUNE_PASS_THREADS = 0
 MS_TUNE_SEG_BLOCKS = 1
 MS_TUNE_HIST_BLOCKS = 2
+MS_TUNE_SMALL_SORT = 3
 
 _lib = None
 _lock = threading.Lock()

@@ -48,28 +48,53 @@ __device__ __forceinline__ uint64_t seg_len(const uint64_t* off, uint64_t s, uin
   return e > b ? e - b : 0;
 }
 
-// 1. plan: work list of non-empty segments, largest size class first.
+// 1. plan: work list of non-empty segments, largest size class first, in
+//    three launches over all segments at once (plan blocks b = 0 .. G-1 take
+//    segments b*1024 + t, stepping by G*1024, in 1a and 1c alike).
 //    ctr[0] = next work item (reset to 0), ctr[1] = number of work items,
-//    ctr[2] = first item of the wave-sized class, ctr[3] = next such item.
-__global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t* __restrict__ off, uint64_t nseg,
-                                                        uint64_t n, uint32_t* worklist, uint32_t* ctr) {
+//    ctr[2] = first item of the wave-sized class (ctr[3] unused).
+constexpr uint32_t kPlanMaxBlocks = 1024;
+
+__device__ __forceinline__ int seg_class(const uint64_t* off, uint64_t s, uint64_t nseg, uint64_t n) {
+  if (s >= nseg) return -1;
+  uint64_t b;
+  const uint64_t len = seg_len(off, s, n, &b);
+  return len ? 63 - __builtin_clzll(len) : -1;  // floor(log2 len); -1: empty
+}
+
+// 1a. row b of `bc`: how many of plan block b's segments fall in each class.
+__global__ __launch_bounds__(1024) void seg_count_kernel(const uint64_t* __restrict__ off, uint64_t nseg,
+                                                         uint64_t n, uint32_t* bc) {
   __shared__ uint32_t s_count[kClasses];
-  __shared__ uint32_t s_base[kClasses];
   const int tid = threadIdx.x;
   if (tid < kClasses) s_count[tid] = 0;
   __syncthreads();
-  for (uint64_t s = tid; s < nseg; s += blockDim.x) {
-    uint64_t b;
-    const uint64_t len = seg_len(off, s, n, &b);
-    if (len) atomicAdd(&s_count[63 - __builtin_clzll(len)], 1u);
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 1024;
+  for (uint64_t s = static_cast<uint64_t>(blockIdx.x) * 1024 + tid; s < nseg; s += stride) {
+    const int c = seg_class(off, s, nseg, n);
+    if (c >= 0) atomicAdd(&s_count[c], 1u);
   }
   __syncthreads();
-  if (tid == 0) {
+  if (tid < kClasses) bc[static_cast<size_t>(blockIdx.x) * kClasses + tid] = s_count[tid];
+}
+
+// 1b. (one block of kClasses threads) the first work-list slot of every
+// (plan block, class): classes largest first, blocks in order within a class.
+__global__ __launch_bounds__(kClasses) void seg_base_kernel(const uint32_t* __restrict__ bc, uint32_t nblocks,
+                                                            uint32_t* boff, uint32_t* ctr) {
+  __shared__ uint32_t s_total[kClasses];
+  __shared__ uint32_t s_first[kClasses];
+  const int c = threadIdx.x;
+  uint32_t total = 0;
+  for (uint32_t b = 0; b < nblocks; ++b) total += bc[static_cast<size_t>(b) * kClasses + c];
+  s_total[c] = total;
+  __syncthreads();
+  if (c == 0) {
     uint32_t run = 0, tiny_begin = 0;
-    for (int c = kClasses - 1; c >= 0; --c) {
-      if (c == kTinyClass) tiny_begin = run;
-      s_base[c] = run;
-      run += s_count[c];
+    for (int k = kClasses - 1; k >= 0; --k) {
+      if (k == kTinyClass) tiny_begin = run;
+      s_first[k] = run;
+      run += s_total[k];
     }
     ctr[0] = 0;
     ctr[1] = run;
@@ -77,10 +102,26 @@ __global__ __launch_bounds__(1024) void seg_plan_kernel(const uint64_t* __restri
     ctr[3] = tiny_begin;
   }
   __syncthreads();
-  for (uint64_t s = tid; s < nseg; s += blockDim.x) {
-    uint64_t b;
-    const uint64_t len = seg_len(off, s, n, &b);
-    if (len) worklist[atomicAdd(&s_base[63 - __builtin_clzll(len)], 1u)] = static_cast<uint32_t>(s);
+  uint32_t run = s_first[c];
+  for (uint32_t b = 0; b < nblocks; ++b) {
+    boff[static_cast<size_t>(b) * kClasses + c] = run;
+    run += bc[static_cast<size_t>(b) * kClasses + c];
+  }
+}
+
+// 1c. plan block b writes its segments from its slots on (any order within a
+// block: segments are sorted independently).
+__global__ __launch_bounds__(1024) void seg_fill_kernel(const uint64_t* __restrict__ off, uint64_t nseg,
+                                                        uint64_t n, const uint32_t* __restrict__ boff,
+                                                        uint32_t* worklist) {
+  __shared__ uint32_t s_next[kClasses];
+  const int tid = threadIdx.x;
+  if (tid < kClasses) s_next[tid] = boff[static_cast<size_t>(blockIdx.x) * kClasses + tid];
+  __syncthreads();
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 1024;
+  for (uint64_t s = static_cast<uint64_t>(blockIdx.x) * 1024 + tid; s < nseg; s += stride) {
+    const int c = seg_class(off, s, nseg, n);
+    if (c >= 0) worklist[atomicAdd(&s_next[c], 1u)] = static_cast<uint32_t>(s);
   }
 }
 
@@ -118,13 +159,45 @@ __device__ __forceinline__ uint64_t tile_diff_bits(const K (&keys)[KPT], int val
   return d;
 }
 
+// A segment of at most one key per lane sorted by one wave with a bitonic
+// network (Batcher's sorting network for 64 inputs: log2(64) merge levels,
+// 21 compare-exchange stages, each a lane exchange).  Every lane carries its
+// key (encoded), its input position and its value; items are ordered by
+// (key, position), so equal keys keep their input order and the result is
+// the stable sort.  Lanes past the segment hold the largest key with
+// positions past it: they end last.
+template <typename K, bool VALS>
+__device__ __forceinline__ void wave_bitonic_sort(K& key, uint32_t& pos, uint32_t& val) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (uint32_t k = 2; k <= static_cast<uint32_t>(kWave); k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      const K ok = __shfl_xor(key, static_cast<int>(j), kWave);
+      const uint32_t op = __shfl_xor(pos, static_cast<int>(j), kWave);
+      uint32_t ov = 0;
+      if constexpr (VALS) ov = __shfl_xor(val, static_cast<int>(j), kWave);
+      const bool ascending = (lane & k) == 0;  // this run of k lanes is sorted upwards
+      const bool lower = (lane & j) == 0;      // this lane is the lower of its pair
+      const bool other_less = ok < key || (ok == key && op < pos);
+      // The lower lane keeps the smaller item of an ascending run, the larger
+      // of a descending one; the upper lane the other.
+      if (lower == ascending ? other_less : !other_less) {
+        key = ok;
+        pos = op;
+        if constexpr (VALS) val = ov;
+      }
+    }
+  }
+}
+
 // 2. sort: persistent workgroups over the work list.
 template <typename K, bool VALS, int THREADS>
 __global__ __launch_bounds__(THREADS) void segmented_kernel(const K* kin, const uint32_t* vin, K* kout,
                                                              uint32_t* vout, K* alt_k, uint32_t* alt_v,
                                                              const uint64_t* __restrict__ off, uint64_t n_total,
                                                              K flip, const uint32_t* __restrict__ worklist,
-                                                             uint32_t* ctr) {
+                                                             uint32_t* ctr, int small_limit) {
   constexpr int kKpt = SegCfg<THREADS>::kKpt;
   constexpr int kTile = SegCfg<THREADS>::kTile;
   constexpr int P = sizeof(K);
@@ -154,24 +227,34 @@ __global__ __launch_bounds__(THREADS) void segmented_kernel(const K* kin, const 
     __syncthreads();
     if (tid == 0) {
       const uint32_t i = atomicAdd(&ctr[0], 1u);
-      if (i < ctr[2]) {
-        s_item = i;
-        s_mode = 0;
-      } else {  // wave-sized segments: one per wave
-        s_item = atomicAdd(&ctr[3], static_cast<uint32_t>(kWaves));
-        s_mode = 1;
-      }
+      s_item = i;
+      s_mode = i < ctr[2] ? 0 : 1;
     }
     __syncthreads();
     const uint32_t item = s_item;
     if (s_mode == 1) {
-      if (item >= ctr[1]) return;
-      const uint32_t mine = item + tid / kWave;
-      if (mine < ctr[1]) {
+      // Only wave-sized segments are left: every wave of the grid takes every
+      // (grid waves)-th of them on its own, with no atomics (one counter would
+      // queue every wave on one address) and no block barrier from here on.
+      const uint32_t nwaves = gridDim.x * kWaves;
+      for (uint32_t mine = ctr[2] + blockIdx.x * kWaves + tid / kWave; mine < ctr[1]; mine += nwaves) {
         uint64_t begin;
         const uint64_t len = seg_len(off, worklist[mine], n_total, &begin);
         const int valid = static_cast<int>(len);  // 1 .. kTinyKeys - 1
         const uint32_t lane = lane_id();
+        if (valid <= small_limit) {  // wave-uniform: one segment per wave
+          const bool mine_real = static_cast<int>(lane) < valid;
+          K key = mine_real ? flip_key(kin[begin + lane], flip) : ~K(0);
+          uint32_t pos = lane;
+          uint32_t val = 0;
+          if constexpr (VALS) val = mine_real ? vin[begin + lane] : 0u;
+          wave_bitonic_sort<K, VALS>(key, pos, val);
+          if (mine_real) {
+            kout[begin + lane] = flip_key(key, flip);
+            if constexpr (VALS) vout[begin + lane] = val;
+          }
+          continue;
+        }
         const int wave = tid / kWave;
         K* wk = s_stage + wave * padded16(kTinyKeys);
         uint32_t* wv = s_vstage + (VALS ? wave * padded16(kTinyKeys) : 0);
@@ -204,7 +287,7 @@ __global__ __launch_bounds__(THREADS) void segmented_kernel(const K* kin, const 
           }
         }
       }
-      continue;
+      return;
     }
     if (item >= ctr[1]) return;
     uint64_t begin;
@@ -331,14 +414,21 @@ __global__ __launch_bounds__(THREADS) void segmented_kernel(const K* kin, const 
 }
 
 struct SegLayout {
-  size_t ctr = 0, worklist = 0, alt_k = 0, alt_v = 0, total = 0;
+  size_t ctr = 0, bc = 0, boff = 0, worklist = 0, alt_k = 0, alt_v = 0, total = 0;
+  uint32_t plan_blocks = 0;
 };
 
 SegLayout seg_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg) {
   SegLayout L;
+  const uint64_t pb = (nseg + 1023) / 1024;
+  L.plan_blocks = static_cast<uint32_t>(pb < kPlanMaxBlocks ? (pb ? pb : 1) : kPlanMaxBlocks);
   size_t off = 0;
   L.ctr = off;
   off += kAlign;
+  L.bc = off;
+  off += align_up(static_cast<size_t>(L.plan_blocks) * kClasses * sizeof(uint32_t));
+  L.boff = off;
+  off += align_up(static_cast<size_t>(L.plan_blocks) * kClasses * sizeof(uint32_t));
   L.worklist = off;
   off += align_up(nseg * sizeof(uint32_t));
   L.alt_k = off;
@@ -358,13 +448,19 @@ ms_status run_segmented(const void* kin, const uint32_t* vin, void* kout, uint32
   uint32_t* worklist = reinterpret_cast<uint32_t*>(ws + L.worklist);
   K* alt_k = reinterpret_cast<K*>(ws + L.alt_k);
   uint32_t* alt_v = VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr;
-  MS_LAUNCH("seg_plan", seg_plan_kernel, 1, 1024, s, off, nseg, n, worklist, ctr);
+  uint32_t* bc = reinterpret_cast<uint32_t*>(ws + L.bc);
+  uint32_t* boff = reinterpret_cast<uint32_t*>(ws + L.boff);
+  MS_LAUNCH("seg_plan", seg_count_kernel, L.plan_blocks, 1024, s, off, nseg, n, bc);
+  MS_LAUNCH("seg_plan", seg_base_kernel, 1, kClasses, s, static_cast<const uint32_t*>(bc), L.plan_blocks, boff, ctr);
+  MS_LAUNCH("seg_plan", seg_fill_kernel, L.plan_blocks, 1024, s, off, nseg, n, static_cast<const uint32_t*>(boff),
+            worklist);
   int64_t want = tune_get(MS_TUNE_SEG_BLOCKS);
   if (want <= 0) want = kPersistentBlocks;
   const uint32_t blocks = static_cast<uint32_t>(nseg < static_cast<uint64_t>(want) ? nseg : want);
+  const int small_limit = static_cast<int>(tune_get(MS_TUNE_SMALL_SORT));  // 0 or kWave
   MS_LAUNCH("seg_sort", (segmented_kernel<K, VALS, kSegThreads>), blocks, kSegThreads, s,
             static_cast<const K*>(kin), vin, static_cast<K*>(kout), vout, alt_k, alt_v, off, n, flip,
-            static_cast<const uint32_t*>(worklist), ctr);
+            static_cast<const uint32_t*>(worklist), ctr, small_limit);
   return MS_OK;
 }
 

@@ -8,7 +8,9 @@ workload class so later runs start from the known best.
 
 Tuned per class:
   whole-list sorts  digit-pass tile (threads x 16 keys) and histogram grid
-  segmented sorts   persistent workgroup count
+  segmented sorts   persistent workgroup count, and whether segments of at
+                    most 64 keys are ordered by a comparison network
+                    (bitonic, one wave) or by radix passes
   serving           the request length above which a request is launched on
                     its own instead of inside a segmented batch
 
@@ -32,6 +34,7 @@ DEFAULT_CACHE = os.environ.get("MI355SORT_TUNE_CACHE",
 PASS_THREADS = (256, 512, 1024)
 HIST_BLOCKS = (128, 256, 512, 1024)
 SEG_BLOCKS = (256, 512, 1024, 2048)
+SMALL_SORT = (64, 0)
 SERVE_THRESHOLDS = (1 << 13, 1 << 16, 1 << 18)
 
 
@@ -140,11 +143,12 @@ class Tuner:
 
         def apply(p):
             N.tune_set(N.MS_TUNE_SEG_BLOCKS, p[0])
+            N.tune_set(N.MS_TUNE_SMALL_SORT, p[1])
 
         def run():
             api.sort_segmented(keys, offsets, vals, out, vout, ws=ws)
 
-        return self._search(key, [(b,) for b in SEG_BLOCKS], apply, run, force)
+        return self._search(key, list(itertools.product(SEG_BLOCKS, SMALL_SORT)), apply, run, force)
 
     def tune_serving(self, run_server: Callable[[int], "object"], force: bool = False,
                      thresholds: Iterable[int] = SERVE_THRESHOLDS) -> dict:

@@ -159,6 +159,11 @@ int main(int argc, char** argv) {
     run_sort<uint32_t>(MS_KEY_I32, 120000, "uniform", false, false, 1024);
     run_sort<uint32_t>(MS_KEY_U32, 70001, "small", false, true, 1024);
     run_segmented<uint32_t>(MS_KEY_I32, {0, 5, 9000, 1, 300, 1000, 64, 2, 900, 17, 18, 19, 20}, true);
+    // segments of at most 64 keys: bitonic network (default) and radix passes
+    run_segmented<uint64_t>(MS_KEY_U64, {64, 63, 1, 2, 3, 33, 65, 0, 16, 48}, true, "few");
+    ms_tune_set(MS_TUNE_SMALL_SORT, 0);
+    run_segmented<uint32_t>(MS_KEY_U32, {64, 63, 1, 2, 3, 33, 65, 0, 16, 48}, true, "few");
+    ms_tune_set(MS_TUNE_SMALL_SORT, 64);
     // A few long segments: whole-device digit passes (empty, one-key and
     // partial-tile segments among them)
     run_segmented<uint32_t>(MS_KEY_I32, {40000, 0, 20000, 1, 50000}, false, "uniform");

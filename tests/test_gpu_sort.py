@@ -215,6 +215,35 @@ def test_sort_segmented_long_in_place():
     assert np.array_equal(host(tk), ek) and np.array_equal(host(tv), ev)
 
 
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("small", [64, 0])
+def test_sort_segmented_tiny_segments(dt, small):
+    """Segments of 1..80 keys: those of at most 64 go through the one-wave
+    bitonic network (ordered by key, then input position) when
+    MS_TUNE_SMALL_SORT is 64, through radix passes when it is 0; both give
+    the oracle's stable sort, keys and pairs, tie-heavy and uniform keys."""
+    from paper_1105_6040_amd import _native as N
+    old = N.tune_get(N.MS_TUNE_SMALL_SORT)
+    N.tune_set(N.MS_TUNE_SMALL_SORT, small)
+    try:
+        g = np.random.default_rng(64 + small)
+        lengths = np.concatenate([g.integers(1, 81, 3000), [0, 64, 65, 1, 63]])
+        g.shuffle(lengths)
+        off = inputs.offsets_from_lengths(lengths)
+        n = int(off[-1])
+        for dist in ("few", "uniform", "extremes"):
+            say(f"tiny segments {dt} small={small} n={n} {dist}")
+            k = inputs.keys(dt, n, dist, seed=small)
+            v = np.arange(n, dtype=np.uint32)
+            assert np.array_equal(host(api.sort_segmented(dev(k), dev(off))), oracle.sort_segmented(k, off)), \
+                (dt, small, dist)
+            ko, vo = api.sort_segmented(dev(k), dev(off), dev(v))
+            ek, ev = oracle.sort_segmented(k, off, v)
+            assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (dt, small, dist)
+    finally:
+        N.tune_set(N.MS_TUNE_SMALL_SORT, old)
+
+
 def test_sort_segmented_in_place_and_edges():
     k = inputs.keys("i32", 50_000, "uniform", seed=5)
     off = np.array([0, 0, 10, 10, 20_000, 20_001, 50_000, 50_000], dtype=np.uint64)
