@@ -380,6 +380,7 @@ def segments_workload(dev, stream, seed=0):
     wall, per = time_steps(lambda: api.sort_segmented(k, toff, keys_out=out, ws=ws), 3, 1, stream)
     ms = sorted(per)[len(per) // 2]
     res = {"segments": int(lengths.size), "keys": n, "ms_median": round(ms, 3), "seg_blocks": tuned["params"][0],
+           "small_segment_network": bool(tuned["params"][1]),
            "GKeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
            "GBps_at_36B_per_key": round(n * 36 / (ms * 1e-3) / 1e9, 1)}
     del k, out, ws, toff

@@ -191,9 +191,18 @@ __device__ __forceinline__ void wave_bitonic_sort(K& key, uint32_t& pos, uint32_
   }
 }
 
-// 2. sort: persistent workgroups over the work list.
+// 2. sort: persistent workgroups over the work list.  32-bit keys without
+// values fit two 512-thread workgroups per CU (4 waves per SIMD, at most 128
+// VGPRs), which the long segments' streaming needs to hide its memory
+// latency; the compiler is held to that (the launch bound's second argument
+// is the minimum number of waves per SIMD).
+template <typename K, bool VALS>
+constexpr int seg_min_waves_per_simd() {
+  return sizeof(K) == 4 && !VALS ? 4 : 1;
+}
+
 template <typename K, bool VALS, int THREADS>
-__global__ __launch_bounds__(THREADS) void segmented_kernel(const K* kin, const uint32_t* vin, K* kout,
+__global__ __launch_bounds__(THREADS, (seg_min_waves_per_simd<K, VALS>())) void segmented_kernel(const K* kin, const uint32_t* vin, K* kout,
                                                              uint32_t* vout, K* alt_k, uint32_t* alt_v,
                                                              const uint64_t* __restrict__ off, uint64_t n_total,
                                                              K flip, const uint32_t* __restrict__ worklist,
