@@ -400,3 +400,61 @@ def test_tie_dense_pairs():
     v = np.arange(k.size, dtype=np.uint32)
     ko, vo = api.sort_pairs(dev(k), dev(v))
     certify_stable_sort(k, host(ko), host(vo))
+
+
+# ---------------------------------------------------------------------------- 64-bit counters
+def _device_keys(n, seed, hi=2**31):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    return torch.randint(0, hi, (n,), dtype=torch.int32, device="cuda", generator=g)
+
+
+def test_big_list_sort_keys_64bit_counters():
+    """2^30 + 5 int32 keys: lists of 2^30 keys and more count in 64-bit words
+    (digit counts, bases and look-back status).  Library witness: torch's
+    sort of the same device array; every key equal."""
+    n = (1 << 30) + 5
+    say(f"big sort_keys n={n}")
+    k = _device_keys(n, 30)
+    out = api.sort_keys(k)
+    assert torch.equal(out, torch.sort(k).values)
+    del out, k
+    torch.cuda.empty_cache()
+
+
+def test_big_list_sort_pairs_64bit_counters():
+    """2^30 + 3 (uint32 key, index) pairs with many ties (keys below 2^20):
+    the O(n) certificate of the stable sort on the device — keys
+    non-decreasing, values a permutation, keys follow their values, equal
+    keys with increasing values."""
+    n = (1 << 30) + 3
+    say(f"big sort_pairs n={n}")
+    k = _device_keys(n, 31, hi=1 << 20).view(torch.uint32)
+    v = torch.arange(n, dtype=torch.int64, device="cuda").to(torch.int32).view(torch.uint32)
+    ko, vo = api.sort_pairs(k, v)
+    ki, vi = ko.view(torch.int32), vo.view(torch.int32).to(torch.int64)
+    assert bool((ki[1:] >= ki[:-1]).all())
+    seen = torch.zeros(n, dtype=torch.bool, device="cuda")
+    seen[vi] = True
+    assert bool(seen.all())
+    assert torch.equal(k.view(torch.int32)[vi], ki)
+    tie = ki[1:] == ki[:-1]
+    assert bool((vi[1:][tie] > vi[:-1][tie]).all())
+    del k, v, ko, vo, ki, vi, seen, tie
+    torch.cuda.empty_cache()
+
+
+def test_big_segments_64bit_counters():
+    """Three segments of 2^30 + 11 keys in all (whole-device segment passes
+    with 64-bit counters): every segment equals torch's sort of it."""
+    lengths = [(1 << 29) + 7, 3, (1 << 29) + 1]
+    off = inputs.offsets_from_lengths(np.array(lengths))
+    n = int(off[-1])
+    say(f"big sort_segmented n={n}")
+    k = _device_keys(n, 32)
+    out = api.sort_segmented(k, dev(off))
+    for s in range(len(lengths)):
+        a, b = int(off[s]), int(off[s + 1])
+        assert torch.equal(out[a:b], torch.sort(k[a:b]).values), s
+    del out, k
+    torch.cuda.empty_cache()
