@@ -204,6 +204,10 @@ int main(int argc, char** argv) {
     run_segmented<uint32_t>(MS_KEY_U32, {7000, 10000, 3}, true);
     run_segmented<uint64_t>(MS_KEY_U64, {5000, 4096, 4097, 0}, true);
   }
+  if (what == "mergebig") {  // lists of 2^22 keys and more: the larger merge tiles (slow on the emulator)
+    run_merge<uint32_t>(MS_KEY_I32, {1u << 21, (1u << 21) + 3, 77, 0, 5});
+    run_merge_split<uint32_t>(MS_KEY_U32, 4 * ((1u << 20) + 1), 4, false, "few");
+  }
   if (what == "all" || what == "merge") {
     run_merge<uint32_t>(MS_KEY_I32, {3000, 0, 2500, 4000, 1});
     run_merge<uint64_t>(MS_KEY_U64, {1000, 2000});

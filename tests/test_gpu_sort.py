@@ -315,6 +315,32 @@ def test_merge_split_parity(dt):
                 assert np.array_equal(host(api.merge_split(dev(rk), p)), host(mk)), (dt, p, s_len, dist)
 
 
+@pytest.mark.parametrize("dt", ["i32", "u64"])
+def test_merge_long_lists(dt):
+    """Lists of 2^22 keys and more merge with the larger tiles: merge_runs
+    over uneven runs and merge_split over equal parts, pairs, tie-heavy keys,
+    against the oracle."""
+    lengths = [1 << 21, (1 << 21) + 3, 77, 0, 5, 300001]
+    off = inputs.offsets_from_lengths(np.array(lengths))
+    n = int(off[-1])
+    say(f"long merge_runs {dt} n={n}")
+    k = inputs.keys(dt, n, "few", seed=22)
+    v = np.arange(n, dtype=np.uint32)
+    rk, rv = oracle.sort_segmented(k, off, v)  # sorted runs (input construction)
+    ek, ev = oracle.merge_runs(rk, off, rv)
+    ko, vo = api.merge_runs(dev(rk), dev(off), dev(rv))
+    assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), dt
+    p = 4
+    n2 = p * ((1 << 20) + 1)
+    say(f"long merge_split {dt} n={n2}")
+    k2 = inputs.keys(dt, n2, "uniform", seed=23)
+    v2 = np.arange(n2, dtype=np.uint32)
+    rk2, rv2 = oracle.sort_segmented(k2, oracle.part_offsets(n2, p), v2)
+    ek2, ev2 = oracle.merge_split(k2, p, v2)
+    ko2, vo2 = api.merge_split(dev(rk2), p, dev(rv2))
+    assert np.array_equal(host(ko2), ek2) and np.array_equal(host(vo2), ev2), dt
+
+
 def test_paper_method_small():
     """100,000 int32 keys, p = 4 equal parts: sort each part, merge (Figure 1)."""
     k, p = inputs.paper_small(0)
