@@ -19,6 +19,7 @@
 // pair and co-rank of its first output itself and merges from global memory,
 // crossing into the next pair if its outputs span a pair boundary.
 #include "ms_device.hpp"
+#include "ms_tile.hpp"
 #include "ms_runtime.hpp"
 
 namespace ms {
@@ -82,8 +83,11 @@ __global__ __launch_bounds__(256) void merge_round_kernel(
   static_assert(kThreads == 256, "the launch bound");
   constexpr int kItems = MergeCfg<K, BIG>::kItems;
   constexpr int kTile = MergeCfg<K, BIG>::kTile;
-  __shared__ K s_out[kTile];
-  __shared__ uint32_t s_outv[VALS ? kTile : 1];
+  // Indexed through pad16 on the tile path (one pad word per 16 entries):
+  // each thread's outputs and its slices of the runs lie ~8-16 entries from
+  // its neighbours', which would otherwise put a wave's accesses in a few banks.
+  __shared__ K s_out[padded16(kTile)];
+  __shared__ uint32_t s_outv[VALS ? padded16(kTile) : 1];
 
   __shared__ uint64_t s_pair[3];  // a0, a1, b1 of the pair holding the whole tile; a0 = ~0: none
   __shared__ uint64_t s_rank[2];
@@ -134,8 +138,8 @@ __global__ __launch_bounds__(256) void merge_round_kernel(
       const int e = q * kThreads + tid;
       if (e < total) {
         const uint64_t from = e < na ? a0 + i0 + e : b0 + (e - na);
-        s_out[e] = src[from];
-        if constexpr (VALS) s_outv[e] = srcv[from];
+        s_out[pad16(e)] = src[from];
+        if constexpr (VALS) s_outv[pad16(e)] = srcv[from];
       }
     }
     __syncthreads();
@@ -149,7 +153,7 @@ __global__ __launch_bounds__(256) void merge_round_kernel(
       int lo = dd > nb ? dd - nb : 0, hi = dd < na ? dd : na;
       while (lo < hi) {
         const int mid = (lo + hi) / 2;
-        if (flip_key(s_out[mid], flip) <= flip_key(s_out[na + dd - 1 - mid], flip))
+        if (flip_key(s_out[pad16(mid)], flip) <= flip_key(s_out[pad16(na + dd - 1 - mid)], flip))
           lo = mid + 1;
         else
           hi = mid;
@@ -158,18 +162,18 @@ __global__ __launch_bounds__(256) void merge_round_kernel(
       cnt = total - dd < kItems ? total - dd : kItems;
       // The heads of both runs stay in registers: one LDS read per output
       // (an index past its run reads a neighbour that is never taken).
-      K ha = s_out[i < kTile ? i : kTile - 1];
-      K hb = s_out[na + k < kTile ? na + k : kTile - 1];
+      K ha = s_out[pad16(i < kTile ? i : kTile - 1)];
+      K hb = s_out[pad16(na + k < kTile ? na + k : kTile - 1)];
 #pragma unroll
       for (int q = 0; q < kItems; ++q) {
         if (q < cnt) {
           const bool take_a = k >= nb || (i < na && flip_key(ha, flip) <= flip_key(hb, flip));
           ok[q] = take_a ? ha : hb;
-          if constexpr (VALS) ov[q] = s_outv[take_a ? i : na + k];
+          if constexpr (VALS) ov[q] = s_outv[pad16(take_a ? i : na + k)];
           i += take_a;
           k += !take_a;
           const int nxt = take_a ? i : na + k;
-          const K h = s_out[nxt < kTile ? nxt : kTile - 1];
+          const K h = s_out[pad16(nxt < kTile ? nxt : kTile - 1)];
           ha = take_a ? h : ha;
           hb = take_a ? hb : h;
         }
@@ -179,8 +183,8 @@ __global__ __launch_bounds__(256) void merge_round_kernel(
 #pragma unroll
     for (int q = 0; q < kItems; ++q) {
       if (q < cnt) {
-        s_out[dd + q] = ok[q];
-        if constexpr (VALS) s_outv[dd + q] = ov[q];
+        s_out[pad16(dd + q)] = ok[q];
+        if constexpr (VALS) s_outv[pad16(dd + q)] = ov[q];
       }
     }
     __syncthreads();
@@ -188,8 +192,8 @@ __global__ __launch_bounds__(256) void merge_round_kernel(
     for (int q = 0; q < kItems; ++q) {
       const int e = q * kThreads + tid;
       if (e < total) {
-        dst[tile_begin + e] = s_out[e];
-        if constexpr (VALS) dstv[tile_begin + e] = s_outv[e];
+        dst[tile_begin + e] = s_out[pad16(e)];
+        if constexpr (VALS) dstv[tile_begin + e] = s_outv[pad16(e)];
       }
     }
     return;
