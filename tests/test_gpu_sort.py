@@ -341,6 +341,39 @@ def test_merge_long_lists(dt):
     assert np.array_equal(host(ko2), ek2) and np.array_equal(host(vo2), ev2), dt
 
 
+@pytest.mark.parametrize("p,s_len", [(7, 1), (64, 1), (5, 2), (2, 1), (3, 3)])
+def test_merge_split_tiny_parts(p, s_len):
+    """Parts of one to three keys: every phase pairs single items (pairs
+    against the oracle's merge-split, tie-heavy keys)."""
+    n = p * s_len
+    k = inputs.keys("i32", n, "few", seed=n)
+    v = np.arange(n, dtype=np.uint32)
+    rk, rv = oracle.sort_segmented(k, oracle.part_offsets(n, p), v)
+    ek, ev = oracle.merge_split(k, p, v)
+    ko, vo = api.merge_split(dev(rk), p, dev(rv))
+    assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (p, s_len)
+
+
+@pytest.mark.parametrize("nseg", [1024, 1025])
+def test_sort_segmented_at_the_segment_pass_limit(nseg):
+    """1,024 segments averaging > 8,192 keys is the largest call the
+    whole-device segment passes take (their tile table fills the LDS copy);
+    1,025 goes to the persistent kernel.  Both against the oracle."""
+    g = np.random.default_rng(nseg)
+    lengths = g.integers(8000, 9000, nseg)
+    lengths[g.integers(0, nseg, 5)] = 0
+    lengths[0] = 40000
+    off = inputs.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    assert n > 8192 * nseg  # long enough on average: only the segment count decides
+    say(f"segment pass limit nseg={nseg} n={n}")
+    k = inputs.keys("u32", n, "uniform", seed=nseg)
+    v = np.arange(n, dtype=np.uint32)
+    ko, vo = api.sort_segmented(dev(k), dev(off), dev(v))
+    ek, ev = oracle.sort_segmented(k, off, v)
+    assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), nseg
+
+
 def test_paper_method_small():
     """100,000 int32 keys, p = 4 equal parts: sort each part, merge (Figure 1)."""
     k, p = inputs.paper_small(0)
