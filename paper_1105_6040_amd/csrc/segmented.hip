@@ -476,6 +476,7 @@ ms_status run_segmented(const void* kin, const uint32_t* vin, void* kout, uint32
 }  // namespace
 
 size_t segmented_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg) {
+  if (nseg == 1) return radix_workspace_bytes(kt, has_vals, n);
   if (segsweep_eligible(n, nseg)) return segsweep_workspace_bytes(kt, has_vals, n, nseg);
   return seg_layout(kt, has_vals, n, nseg).total;
 }
@@ -483,6 +484,9 @@ size_t segmented_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint
 ms_status segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
                          const uint64_t* offsets, uint64_t nseg, uint64_t n, ms_key_type kt, void* ws,
                          size_t ws_bytes, hipStream_t s) {
+  // One segment is the whole list (offsets are {0, n} by contract): the
+  // whole-list sort.
+  if (nseg == 1) return radix_sort(keys_in, vals_in, keys_out, vals_out, n, kt, ws, ws_bytes, s);
   // A few long segments: whole-device digit passes over all of them (the
   // host knows only the counts, which decide).
   if (segsweep_eligible(n, nseg))
