@@ -363,12 +363,18 @@ __global__ __launch_bounds__(THREADS, (seg_min_waves_per_simd<K, VALS>())) void 
       const uint32_t base = block_exclusive_scan_radix<THREADS>(tid < kRadix ? s_hist[p][tid] : 0u, s_cscan, &total);
       if (tid < kRadix) s_run[tid] = base;
 
+      // The next tile's keys are loaded into the registers the sorted tile
+      // has left, so that they arrive while this tile is scattered; barriers
+      // inside the loop guard LDS only and do not wait for those loads.
+      auto tile_valid = [&](uint64_t t) {
+        const uint64_t rem = len - t;
+        return rem < static_cast<uint64_t>(kTile) ? static_cast<int>(rem) : kTile;
+      };
+      load_blocked<K, VALS>(src, srcv, begin, tile_valid(0), in_flip, keys, vals);
       for (uint64_t t0 = 0; t0 < len; t0 += kTile) {
-        const uint64_t rem = len - t0;
-        const int valid = rem < static_cast<uint64_t>(kTile) ? static_cast<int>(rem) : kTile;
-        load_blocked<K, VALS>(src, srcv, begin + t0, valid, in_flip, keys, vals);
+        const int valid = tile_valid(t0);
         for (int d = tid; d < kRadix; d += THREADS) s_thist[d] = 0;
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int j = 0; j < kKpt; ++j) {
           const uint32_t d = digit_of(keys[j], shift);
@@ -379,20 +385,22 @@ __global__ __launch_bounds__(THREADS, (seg_min_waves_per_simd<K, VALS>())) void 
             atomicAdd(&s_thist[d], 1u);
           }
         }
-        __syncthreads();
+        lds_barrier();
         const uint32_t cnt = tid < kRadix ? s_thist[tid] : 0u;
         tile_sort_digit<THREADS, kKpt, VALS>(keys, vals, shift, s_stage, s_vstage, s_counts, s_scan, false);
+        if (t0 + kTile < len) load_blocked<K, VALS>(src, srcv, begin + t0 + kTile, tile_valid(t0 + kTile), in_flip,
+                                                    keys, vals);
         uint32_t tile_total;
         const uint32_t start = block_exclusive_scan_radix<THREADS>(cnt, s_cscan, &tile_total);
         if (tid < kRadix) s_doff[tid] = s_run[tid] - start;
-        __syncthreads();
+        lds_barrier();
         for (int i = tid; i < valid; i += THREADS) {
           const K k = s_stage[pad16(i)];
           const uint64_t o = begin + static_cast<uint32_t>(s_doff[digit_of(k, shift)] + static_cast<uint32_t>(i));
           dst[o] = k ^ out_flip;
           if constexpr (VALS) dstv[o] = s_vstage[pad16(i)];
         }
-        __syncthreads();
+        lds_barrier();
         if (tid < kRadix) s_run[tid] += cnt;
       }
       // This workgroup reads what it just wrote in the next pass.
