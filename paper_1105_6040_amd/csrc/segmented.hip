@@ -34,7 +34,6 @@ struct SegCfg {
   static constexpr int kTile = kThreads * kKpt;
 };
 constexpr int kSegThreads = 512;
-constexpr int kSegTile = SegCfg<kSegThreads>::kTile;
 constexpr int kPersistentBlocks = 1024;
 constexpr int kClasses = 64;
 constexpr int kTinyClass = 9;  // floor(log2 len) <= 9: fewer than 1,024 keys, one wave
