@@ -624,51 +624,97 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// 5. The digit passes of sort_segmented for a few long segments: the paper's
-// parts sorted by the whole device at once instead of one workgroup each.
+// 5. The digit passes of sort_segmented for long segments: the paper's parts
+// sorted by the whole device at once instead of one workgroup each.
 //
 // Every segment is cut into kTile-key tiles from its own start (its last tile
-// is partial) and the tiles of all segments are numbered in segment order.  A
-// tile takes its digit bases from its own segment's histograms, and the
-// segment's first tile publishes INCLUSIVE at once, so that the look-back of
-// every other tile ends inside its segment.  All passes run (no trivial-pass
-// skip): even P ping-pongs keys_in -> workspace -> keys_out -> ... -> keys_out.
+// is partial) and the tiles of all segments are numbered in segment order; a
+// table holds one record per tile.  A tile takes its digit bases from its own
+// segment's histograms, and the segment's first tile publishes INCLUSIVE at
+// once, so that the look-back of every other tile ends inside its segment.  A
+// segment of one tile needs neither histograms nor look-back: its sorted tile
+// is stored in place.  All passes run (no trivial-pass skip): even P
+// ping-pongs keys_in -> workspace -> keys_out -> ... -> keys_out.
 constexpr int kSegSweepThreads = 512;
-constexpr uint32_t kSegSweepMaxSegments = 1024;
 // Used when the segments average more keys than one workgroup sorts in LDS
 // (8,192): shorter ones are sorted faster by one workgroup each.
 constexpr uint64_t kSegSweepMinAverage = 8192;
 using SegSweepCfg = PassCfg<kSegSweepThreads>;
 
-// Segment of tile t: the s with tile_start[s] <= t < tile_start[s + 1]
-// (a non-empty segment; tile_start[nseg] is the tile count, above t).
-__device__ __forceinline__ uint32_t segment_of_tile(const uint32_t* tile_start, uint32_t nseg, uint32_t t) {
-  uint32_t lo = 0, hi = nseg;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) / 2;
-    if (tile_start[mid] <= t)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
+// One tile of the segment passes.  `count` holds the tile's key count
+// (1 .. kTile) and two flags.
+struct SegTile {
+  uint64_t begin;  // index of the tile's first key
+  uint32_t count;
+  uint32_t seg;
+};
+constexpr uint32_t kTileFirst = 1u << 31;  // the segment's first tile
+constexpr uint32_t kTileOnly = 1u << 30;   // the segment's only tile
+constexpr uint32_t kTileCountMask = kTileOnly - 1;
+
+// The tile table is planned in chunks of kSegChunk segments, one block each.
+constexpr int kSegPlanThreads = 256;
+constexpr int kSegPlanPerThread = 8;
+constexpr uint32_t kSegChunk = kSegPlanThreads * kSegPlanPerThread;
+
+__device__ __forceinline__ uint32_t segment_tiles(const uint64_t* off, uint64_t s) {
+  constexpr int kTile = SegSweepCfg::kTile;
+  return static_cast<uint32_t>((off[s + 1] - off[s] + kTile - 1) / kTile);
 }
 
-// Tile table and pass plan (one block of 1,024 threads, nseg <= 1,024).
+// Tiles of this block's segments, each thread summing kSegPlanPerThread
+// consecutive segments; returns the thread's exclusive start inside the block
+// and the block total in *total.
+__device__ __forceinline__ uint32_t chunk_tiles(const uint64_t* off, uint32_t nseg, uint32_t* s_scan,
+                                                uint32_t* total) {
+  const uint32_t s0 = blockIdx.x * kSegChunk + threadIdx.x * kSegPlanPerThread;
+  uint32_t mine = 0;
+#pragma unroll
+  for (int i = 0; i < kSegPlanPerThread; ++i)
+    if (s0 + i < nseg) mine += segment_tiles(off, s0 + i);
+  const uint32_t start = block_exclusive_scan<kSegPlanThreads>(mine, s_scan);
+  __syncthreads();
+  if (threadIdx.x == kSegPlanThreads - 1) s_scan[0] = start + mine;
+  __syncthreads();
+  *total = s_scan[0];
+  __syncthreads();
+  return start;
+}
+
+// Plan step 1: tiles per chunk of segments.
+__global__ __launch_bounds__(kSegPlanThreads) void segsweep_count_kernel(const uint64_t* __restrict__ off,
+                                                                        uint32_t nseg,
+                                                                        uint32_t* __restrict__ chunk_start) {
+  __shared__ uint32_t s_scan[kSegPlanThreads / kWave];
+  uint32_t total;
+  chunk_tiles(off, nseg, s_scan, &total);
+  if (threadIdx.x == 0) chunk_start[blockIdx.x] = total;
+}
+
+// Plan step 2 (one block): chunk starts by an exclusive scan of their tile
+// counts, the tile count, and the pass plan.
 template <typename K, bool VALS>
-__global__ __launch_bounds__(1024) void segsweep_plan_kernel(const uint64_t* __restrict__ off, uint32_t nseg,
-                                                             uint32_t* __restrict__ tile_start, SortPlan* plan,
+__global__ __launch_bounds__(1024) void segsweep_plan_kernel(uint32_t* __restrict__ chunk_start, uint32_t chunks,
+                                                             uint32_t* __restrict__ num_tiles, SortPlan* plan,
                                                              Buffers buf) {
-  constexpr int kTile = SegSweepCfg::kTile;
   constexpr int P = sizeof(K);
   __shared__ uint32_t s_scan[1024 / kWave];
+  __shared__ uint32_t s_carry;
   const int tid = threadIdx.x;
-  const uint32_t tiles =
-      static_cast<uint32_t>(tid) < nseg ? static_cast<uint32_t>((off[tid + 1] - off[tid] + kTile - 1) / kTile) : 0u;
-  const uint32_t start = block_exclusive_scan<1024>(tiles, s_scan);
-  if (static_cast<uint32_t>(tid) < nseg) tile_start[tid] = start;
-  if (static_cast<uint32_t>(tid) == nseg - 1) tile_start[nseg] = start + tiles;
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (uint32_t c0 = 0; c0 < chunks; c0 += 1024) {
+    const uint32_t c = c0 + tid;
+    const uint32_t v = c < chunks ? chunk_start[c] : 0u;
+    const uint32_t ex = block_exclusive_scan<1024>(v, s_scan);
+    const uint32_t carry = s_carry;
+    if (c < chunks) chunk_start[c] = carry + ex;
+    __syncthreads();
+    if (tid == 1023) s_carry = carry + ex + v;
+    __syncthreads();
+  }
   if (tid != 0) return;
+  *num_tiles = s_carry;
   for (int p = 0; p < kMaxPasses; ++p) {
     PassPlan pp = {};
     if (p < P) {
@@ -691,24 +737,74 @@ __global__ __launch_bounds__(1024) void segsweep_plan_kernel(const uint64_t* __r
   plan->num_active = P;
 }
 
-// Digit histograms of every segment (all P digit positions): each block
-// counts a contiguous range of tiles in LDS and adds its counts to the
-// segment's row whenever the segment changes.
+// Plan step 3: the records of this chunk's tiles, written by all threads of
+// the block (a tile finds its segment by a binary search over the chunk's
+// segment starts in LDS).
+__global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const uint64_t* __restrict__ off,
+                                                                       uint32_t nseg,
+                                                                       const uint32_t* __restrict__ chunk_start,
+                                                                       SegTile* __restrict__ tiles) {
+  constexpr int kTile = SegSweepCfg::kTile;
+  __shared__ uint32_t s_scan[kSegPlanThreads / kWave];
+  __shared__ uint32_t s_start[kSegChunk + 1];  // tile start of each segment of the chunk, block-relative
+  const uint32_t first_seg = blockIdx.x * kSegChunk;
+  const uint32_t nloc = nseg - first_seg < kSegChunk ? nseg - first_seg : kSegChunk;
+  uint32_t total;
+  const uint32_t start = chunk_tiles(off, nseg, s_scan, &total);
+  {
+    const uint32_t l0 = threadIdx.x * kSegPlanPerThread;
+    uint32_t run = start;
+#pragma unroll
+    for (int i = 0; i < kSegPlanPerThread; ++i)
+      if (l0 + i < nloc) {
+        s_start[l0 + i] = run;
+        run += segment_tiles(off, first_seg + l0 + i);
+      }
+    if (threadIdx.x == 0) s_start[nloc] = total;
+  }
+  __syncthreads();
+  const uint32_t base = chunk_start[blockIdx.x];
+  for (uint32_t t = threadIdx.x; t < total; t += kSegPlanThreads) {
+    // The last local segment whose start is <= t: a non-empty one, since
+    // t < its successor's start.
+    uint32_t lo = 0, hi = nloc;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (s_start[mid] <= t)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const uint32_t s = first_seg + lo;
+    const uint32_t j = t - s_start[lo];
+    const uint64_t b = off[s] + static_cast<uint64_t>(j) * kTile;
+    const uint64_t e = off[s + 1];
+    const uint32_t cnt = static_cast<uint32_t>(e - b < static_cast<uint64_t>(kTile) ? e - b : kTile);
+    const bool only = s_start[lo + 1] - s_start[lo] == 1;
+    SegTile r;
+    r.begin = b;
+    r.count = cnt | (j == 0 ? kTileFirst : 0u) | (only ? kTileOnly : 0u);
+    r.seg = s;
+    tiles[base + t] = r;
+  }
+}
+
+// Digit histograms of every segment of more than one tile (all P digit
+// positions): each block counts a contiguous range of tiles in LDS and adds
+// its counts to the segment's row whenever the segment changes.
 template <typename K, typename C>
 __global__ __launch_bounds__(256) void segsweep_hist_kernel(const K* __restrict__ keys, K flip,
-                                                            const uint64_t* __restrict__ off, uint32_t nseg,
-                                                            const uint32_t* __restrict__ tile_start,
+                                                            const SegTile* __restrict__ tiles,
+                                                            const uint32_t* __restrict__ num_tiles,
                                                             C* __restrict__ seg_hist) {
   constexpr int P = sizeof(K);
   constexpr int kCopies = 64 / P;
-  constexpr int kTile = SegSweepCfg::kTile;
+  constexpr int kInFlight = 16;  // loads per thread issued before their counts
   __shared__ uint32_t h[P * kRadix * kCopies];
-  __shared__ uint32_t s_tstart[kSegSweepMaxSegments + 1];
   const int tid = threadIdx.x;
-  for (uint32_t i = tid; i <= nseg; i += 256) s_tstart[i] = tile_start[i];
   for (int i = tid; i < P * kRadix * kCopies; i += 256) h[i] = 0;
   __syncthreads();
-  const uint32_t total = s_tstart[nseg];
+  const uint32_t total = *num_tiles;
   const uint32_t t0 = static_cast<uint32_t>(static_cast<uint64_t>(total) * blockIdx.x / gridDim.x);
   const uint32_t t1 = static_cast<uint32_t>(static_cast<uint64_t>(total) * (blockIdx.x + 1) / gridDim.x);
   const uint32_t copy = lane_id() % kCopies;
@@ -727,39 +823,54 @@ __global__ __launch_bounds__(256) void segsweep_hist_kernel(const K* __restrict_
   };
   uint32_t cur = ~0u;
   for (uint32_t t = t0; t < t1; ++t) {
-    const uint32_t s = segment_of_tile(s_tstart, nseg, t);
-    if (s != cur && cur != ~0u) flush(cur);
-    cur = s;
-    const uint64_t b = off[s] + static_cast<uint64_t>(t - s_tstart[s]) * kTile;
-    const uint64_t e = b + kTile < off[s + 1] ? b + kTile : off[s + 1];
-    for (uint64_t i = b + tid; i < e; i += 256) {
-      const K k = flip_key(keys[i], flip);
+    const SegTile r = tiles[t];
+    if (r.count & kTileOnly) continue;  // uniform over the block
+    if (r.seg != cur && cur != ~0u) flush(cur);
+    cur = r.seg;
+    const uint32_t cnt = r.count & kTileCountMask;
+    const K* src = keys + r.begin;
+    for (uint32_t i0 = 0; i0 < cnt; i0 += 256 * kInFlight) {
+      K v[kInFlight];
 #pragma unroll
-      for (int p = 0; p < P; ++p) atomicAdd(&h[(p * kRadix + digit_of(k, 8 * p)) * kCopies + copy], 1u);
+      for (int q = 0; q < kInFlight; ++q) {
+        const uint32_t i = i0 + q * 256 + tid;
+        v[q] = i < cnt ? src[i] : K(0);
+      }
+#pragma unroll
+      for (int q = 0; q < kInFlight; ++q) {
+        if (i0 + q * 256 + tid < cnt) {
+          const K k = flip_key(v[q], flip);
+#pragma unroll
+          for (int p = 0; p < P; ++p) atomicAdd(&h[(p * kRadix + digit_of(k, 8 * p)) * kCopies + copy], 1u);
+        }
+      }
     }
   }
   if (cur != ~0u) flush(cur);
 }
 
 // Digit bases: row (s, p) of seg_base = off[s] + exclusive scan of the
-// segment's digit-p counts.  One block per row.
+// segment's digit-p counts.  One block per row; one-tile segments have no
+// histogram and need no bases.
 template <typename C>
 __global__ __launch_bounds__(256) void segsweep_base_kernel(const uint64_t* __restrict__ off, int P,
                                                             const C* __restrict__ seg_hist, C* __restrict__ seg_base) {
   __shared__ C s_scan[kRadix / kWave];
   const uint32_t row = blockIdx.x;
+  const uint64_t s = row / P;
+  if (off[s + 1] - off[s] <= static_cast<uint64_t>(SegSweepCfg::kTile)) return;
   const C c = seg_hist[static_cast<size_t>(row) * kRadix + threadIdx.x];
   C total;
   const C ex = block_exclusive_scan_radix<256>(c, s_scan, &total);
-  seg_base[static_cast<size_t>(row) * kRadix + threadIdx.x] = static_cast<C>(off[row / P]) + ex;
+  seg_base[static_cast<size_t>(row) * kRadix + threadIdx.x] = static_cast<C>(off[s]) + ex;
 }
 
 // One digit pass over the tiles of every segment (persistent workgroups,
 // tiles by ticket as in onesweep_kernel, without agents or LDS prefetch).
 template <typename K, bool VALS, typename C, typename S>
 __global__ __launch_bounds__(kSegSweepThreads) void segsweep_pass_kernel(
-    const SortPlan* __restrict__ plan, int pass, const uint64_t* __restrict__ off, uint32_t nseg,
-    const uint32_t* __restrict__ tile_start, K flip, const C* __restrict__ seg_base, uint32_t* tile_counter,
+    const SortPlan* __restrict__ plan, int pass, const SegTile* __restrict__ tiles,
+    const uint32_t* __restrict__ num_tiles_p, K flip, const C* __restrict__ seg_base, uint32_t* tile_counter,
     S* status_cur, S* status_next) {
   constexpr int kThreads = kSegSweepThreads;
   constexpr int kKpt = SegSweepCfg::kKpt;
@@ -778,13 +889,11 @@ __global__ __launch_bounds__(kSegSweepThreads) void segsweep_pass_kernel(
   __shared__ uint32_t s_scan[kThreads / kWave];
   __shared__ C s_cscan[kRadix / kWave];
   __shared__ uint32_t s_ticket;
-  __shared__ uint32_t s_tstart[kSegSweepMaxSegments + 1];
 
   const int tid = threadIdx.x;
-  for (uint32_t i = tid; i <= nseg; i += kThreads) s_tstart[i] = tile_start[i];
   if (tid == 0) s_ticket = atomicAdd(tile_counter, 1u);
   __syncthreads();
-  const uint32_t num_tiles = s_tstart[nseg];
+  const uint32_t num_tiles = *num_tiles_p;
   uint32_t tile = s_ticket;
   if (tile >= num_tiles) return;
 
@@ -798,18 +907,18 @@ __global__ __launch_bounds__(kSegSweepThreads) void segsweep_pass_kernel(
   const K out_flip = pp.last ? flip : K(0);
   const K pad = ~K(0) ^ in_flip;  // decodes to all-ones: sorts after every real key of the tile
 
-  // The tile's segment, its index in the segment, first key and the
-  // segment's end.
-  uint32_t seg = segment_of_tile(s_tstart, nseg, tile);
-  uint32_t j = tile - s_tstart[seg];
-  C tile_base = static_cast<C>(off[seg]) + static_cast<C>(j) * kTile;
-  C seg_end = static_cast<C>(off[seg + 1]);
+  // The tile's record: first key, key count and flags, segment.
+  SegTile r = tiles[tile];
+  C tile_base = static_cast<C>(r.begin);
+  C tile_end = tile_base + static_cast<C>(r.count & kTileCountMask);
 
   K keys[kKpt];
   uint32_t vals[kKpt];
-  load_tile_keys<K, VALS, C, kKpt>(src, src_v, tile_base + static_cast<C>(tid) * kKpt, seg_end, pad, keys, vals);
+  load_tile_keys<K, VALS, C, kKpt>(src, src_v, tile_base + static_cast<C>(tid) * kKpt, tile_end, pad, keys, vals);
 
   while (true) {
+    const bool first = (r.count & kTileFirst) != 0;
+    const bool only = (r.count & kTileOnly) != 0;
 #pragma unroll
     for (int q = 0; q < kKpt; ++q) keys[q] = flip_key(keys[q], in_flip);
     if (status_next)
@@ -832,19 +941,20 @@ __global__ __launch_bounds__(kSegSweepThreads) void segsweep_pass_kernel(
     }
     lds_barrier();
 
-    // A segment's first tile has no predecessor in its segment.
+    // A segment's first tile has no predecessor in its segment; a segment's
+    // only tile has no successor either, and publishes nothing.
     S* st = status_cur + static_cast<size_t>(tile) * kRadix + tid;
     uint32_t cnt = 0;
     if (tid < kRadix) {
       cnt = s_hist[tid];
-      status_store(st, (j == 0 ? St::kInc : St::kAgg) | static_cast<S>(cnt));
+      if (!only) status_store(st, (first ? St::kInc : St::kAgg) | static_cast<S>(cnt));
     }
     uint32_t ticket = 0;
     if (tid == 0) ticket = atomicInc(tile_counter, ~0u);
 
     tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift, s_stage, s_vstage, s_counts, s_scan, true);
     S pred = 0;
-    if (tid < kRadix && j != 0) pred = status_load(st - kRadix);
+    if (tid < kRadix && !first) pred = status_load(st - kRadix);
     tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift + kSubBits, s_stage, s_vstage, s_counts, s_scan, false);
 
     if (tid == 0) s_ticket = ticket;
@@ -854,24 +964,27 @@ __global__ __launch_bounds__(kSegSweepThreads) void segsweep_pass_kernel(
     // The next tile's keys load into the registers during the look-back.
     const uint32_t next = s_ticket;
     const bool more = next < num_tiles;
-    const uint32_t cur_seg = seg, cur_j = j;
-    const C cur_base = tile_base, cur_end = seg_end;
+    const uint32_t cur_seg = r.seg;
+    const C cur_base = tile_base, cur_end = tile_end;
     if (more) {
-      seg = segment_of_tile(s_tstart, nseg, next);
-      j = next - s_tstart[seg];
-      tile_base = static_cast<C>(off[seg]) + static_cast<C>(j) * kTile;
-      seg_end = static_cast<C>(off[seg + 1]);
-      load_tile_keys<K, VALS, C, kKpt>(src, src_v, tile_base + static_cast<C>(tid) * kKpt, seg_end, pad, keys, vals);
+      r = tiles[next];
+      tile_base = static_cast<C>(r.begin);
+      tile_end = tile_base + static_cast<C>(r.count & kTileCountMask);
+      load_tile_keys<K, VALS, C, kKpt>(src, src_v, tile_base + static_cast<C>(tid) * kKpt, tile_end, pad, keys, vals);
     }
 
     if (tid < kRadix) {
-      C excl = 0;
-      if (cur_j != 0) {
-        excl = (pred & St::kFlagMask) == St::kInc ? static_cast<C>(pred & St::kValMask)
-                                                  : lookback<C, S, 16>(st, tile, kRadix);
-        status_store(st, St::kInc | static_cast<S>(excl + cnt));
+      if (only) {
+        s_doff[tid] = cur_base;  // the segment's digit-d keys start at cur_base + start[d]: the tile in place
+      } else {
+        C excl = 0;
+        if (!first) {
+          excl = (pred & St::kFlagMask) == St::kInc ? static_cast<C>(pred & St::kValMask)
+                                                    : lookback<C, S, 16>(st, tile, kRadix);
+          status_store(st, St::kInc | static_cast<S>(excl + cnt));
+        }
+        s_doff[tid] = seg_base[(static_cast<size_t>(cur_seg) * P + pass) * kRadix + tid] + excl - start;
       }
-      s_doff[tid] = seg_base[(static_cast<size_t>(cur_seg) * P + pass) * kRadix + tid] + excl - start;
     }
     lds_barrier();
 
@@ -1100,12 +1213,13 @@ ms_status dispatch(const void* kin, const uint32_t* vin, void* kout, uint32_t* v
 }
 
 // ---------------------------------------------------------------------------
-// Segmented digit passes (few long segments).
+// Segmented digit passes (long segments).
 struct SegSweepLayout {
-  size_t plan = 0, ctrs = 0, hist = 0, base = 0, tstart = 0, status0 = 0, status1 = 0, alt_k = 0, alt_v = 0,
-         total = 0;
+  size_t plan = 0, ctrs = 0, hist = 0, base = 0, chunks = 0, records = 0, status0 = 0, status1 = 0, alt_k = 0,
+         alt_v = 0, total = 0;
   size_t ctrs_hist_bytes = 0, status_bytes = 0;
   uint64_t tiles = 0;  // bound on the tile count: every segment adds at most one partial tile
+  uint32_t num_chunks = 0;
   bool big = false;
 };
 
@@ -1116,18 +1230,21 @@ SegSweepLayout segsweep_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64
   L.big = n >= (1ull << 30);
   const size_t cb = L.big ? 8 : 4;
   L.tiles = (n + SegSweepCfg::kTile - 1) / SegSweepCfg::kTile + nseg;
+  L.num_chunks = static_cast<uint32_t>((nseg + kSegChunk - 1) / kSegChunk);
   size_t off = 0;
   L.plan = off;
   off += align_up(sizeof(SortPlan));
-  L.ctrs = off;  // counters and histograms are cleared together
+  L.ctrs = off;  // counters and histograms are cleared together; ctrs[0] receives the tile count
   off += align_up((1 + kMaxPasses) * sizeof(uint32_t));
   L.hist = off;
   off += align_up(nseg * P * kRadix * cb);
   L.ctrs_hist_bytes = off - L.ctrs;
   L.base = off;
   off += align_up(nseg * P * kRadix * cb);
-  L.tstart = off;
-  off += align_up((nseg + 1) * sizeof(uint32_t));
+  L.chunks = off;
+  off += align_up(static_cast<size_t>(L.num_chunks) * sizeof(uint32_t));
+  L.records = off;
+  off += align_up(static_cast<size_t>(L.tiles) * sizeof(SegTile));
   L.status_bytes = align_up(static_cast<size_t>(L.tiles) * kRadix * cb);
   L.status0 = off;
   off += L.status_bytes;
@@ -1151,16 +1268,22 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   uint32_t* ctrs = reinterpret_cast<uint32_t*>(ws + L.ctrs);
   C* hist = reinterpret_cast<C*>(ws + L.hist);
   C* base = reinterpret_cast<C*>(ws + L.base);
-  uint32_t* tstart = reinterpret_cast<uint32_t*>(ws + L.tstart);
+  uint32_t* chunk_start = reinterpret_cast<uint32_t*>(ws + L.chunks);
+  SegTile* records = reinterpret_cast<SegTile*>(ws + L.records);
   S* status[2] = {reinterpret_cast<S*>(ws + L.status0), reinterpret_cast<S*>(ws + L.status1)};
+  const uint32_t* num_tiles = ctrs;
 
   MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), L.ctrs_hist_bytes / 16,
             reinterpret_cast<uint4*>(ws + L.status0), L.status_bytes / 16);
   Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
-  MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, 1024, s, off, nseg, tstart, plan, buf);
+  MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, chunk_start);
+  MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, 1024, s, chunk_start, L.num_chunks, ctrs, plan,
+            buf);
+  MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg,
+            static_cast<const uint32_t*>(chunk_start), records);
   const uint64_t hblocks = std::min<uint64_t>(L.tiles, 2 * device_cus(256));
   MS_LAUNCH("segsweep_hist", (segsweep_hist_kernel<K, C>), static_cast<uint32_t>(hblocks), 256, s,
-            static_cast<const K*>(kin), flip, off, nseg, static_cast<const uint32_t*>(tstart), hist);
+            static_cast<const K*>(kin), flip, static_cast<const SegTile*>(records), num_tiles, hist);
   MS_LAUNCH("segsweep_base", segsweep_base_kernel<C>, nseg * P, 256, s, off, P, static_cast<const C*>(hist), base);
   const uint64_t blocks = std::min<uint64_t>(
       L.tiles, resident_blocks(reinterpret_cast<const void*>(&segsweep_pass_kernel<K, VALS, C, S>),
@@ -1168,9 +1291,8 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   for (int p = 0; p < P; ++p) {
     S* next = p + 1 < P ? status[(p + 1) & 1] : nullptr;
     MS_LAUNCH("segsweep_pass", (segsweep_pass_kernel<K, VALS, C, S>), static_cast<uint32_t>(blocks),
-              kSegSweepThreads, s, static_cast<const SortPlan*>(plan), p, off, nseg,
-              static_cast<const uint32_t*>(tstart), flip, static_cast<const C*>(base), ctrs + 1 + p, status[p & 1],
-              next);
+              kSegSweepThreads, s, static_cast<const SortPlan*>(plan), p, static_cast<const SegTile*>(records),
+              num_tiles, flip, static_cast<const C*>(base), ctrs + 1 + p, status[p & 1], next);
   }
   return MS_OK;
 }
@@ -1210,7 +1332,11 @@ ms_status radix_sort(const void* keys_in, const uint32_t* vals_in, void* keys_ou
 }
 
 bool segsweep_eligible(uint64_t n, uint64_t nseg) {
-  return nseg >= 1 && nseg <= kSegSweepMaxSegments && n > kSegSweepMinAverage * nseg;
+  // Tile numbers and segment ids are 32-bit; the base kernel runs one block
+  // per (segment, digit position) in one grid dimension.
+  if (nseg < 1 || nseg * kMaxPasses >= (1ull << 31)) return false;
+  const uint64_t tiles = (n + SegSweepCfg::kTile - 1) / SegSweepCfg::kTile + nseg;
+  return n > kSegSweepMinAverage * nseg && tiles < (1ull << 32);
 }
 
 size_t segsweep_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg) {

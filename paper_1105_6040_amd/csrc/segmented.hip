@@ -494,8 +494,8 @@ ms_status segmented_sort(const void* keys_in, const uint32_t* vals_in, void* key
   // One segment is the whole list (offsets are {0, n} by contract): the
   // whole-list sort.
   if (nseg == 1) return radix_sort(keys_in, vals_in, keys_out, vals_out, n, kt, ws, ws_bytes, s);
-  // A few long segments: whole-device digit passes over all of them (the
-  // host knows only the counts, which decide).
+  // Long segments (more than 8,192 keys on average): whole-device digit
+  // passes over all of them (the host knows only the counts, which decide).
   if (segsweep_eligible(n, nseg))
     return segsweep_sort(keys_in, vals_in, keys_out, vals_out, offsets, nseg, n, kt, ws, ws_bytes, s);
   const bool vals = vals_in != nullptr;

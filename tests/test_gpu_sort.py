@@ -183,9 +183,9 @@ LONG_SEGMENT_CASES = [
 
 @pytest.mark.parametrize("dt", DTYPES)
 def test_sort_segmented_long_segments(dt):
-    """At most 1,024 segments averaging >= 16,384 keys take whole-device digit
-    passes (tiles cut from each segment's start, per-segment digit bases, a
-    look-back that ends at the segment's first tile).  Keys and pairs against
+    """Segments averaging > 8,192 keys take whole-device digit passes (tiles
+    cut from each segment's start, per-segment digit bases, a look-back that
+    ends at the segment's first tile).  Keys and pairs against
     the oracle, also through a view one key into the buffer (unaligned
     tiles)."""
     for ci, lengths in enumerate(LONG_SEGMENT_CASES):
@@ -354,24 +354,46 @@ def test_merge_split_tiny_parts(p, s_len):
     assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), (p, s_len)
 
 
-@pytest.mark.parametrize("nseg", [1024, 1025])
-def test_sort_segmented_at_the_segment_pass_limit(nseg):
-    """1,024 segments averaging > 8,192 keys is the largest call the
-    whole-device segment passes take (their tile table fills the LDS copy);
-    1,025 goes to the persistent kernel.  Both against the oracle."""
-    g = np.random.default_rng(nseg)
-    lengths = g.integers(8000, 9000, nseg)
-    lengths[g.integers(0, nseg, 5)] = 0
-    lengths[0] = 40000
+def many_segment_lengths(nseg, nlong, seed):
+    """nseg lengths averaging > 8,192: short ones (0 .. 9,000 keys, one tile
+    or two, empty ones among them) with nlong long ones (40,000 .. 140,000)
+    interleaved at random positions."""
+    g = np.random.default_rng(seed)
+    lengths = g.integers(0, 9001, nseg)
+    lengths[g.integers(0, nseg, 7)] = 0
+    lengths[g.integers(0, nseg, 7)] = 8192  # exactly one full tile
+    lengths[g.choice(nseg, nlong, replace=False)] = g.integers(40000, 140001, nlong)
+    return lengths
+
+
+@pytest.mark.parametrize("nseg,nlong", [(1025, 60), (2048, 130), (2049, 130), (4700, 320)])
+def test_sort_segmented_many_long_segments(nseg, nlong):
+    """Segment passes over thousands of segments: the tile table is planned in
+    chunks of 2,048 segments (one, exactly one, just over one and three
+    chunks here), one-tile segments are stored in place without histograms,
+    the rest take per-segment bases and a look-back that ends at their first
+    tile.  Pairs against the oracle."""
+    lengths = many_segment_lengths(nseg, nlong, nseg)
     off = inputs.offsets_from_lengths(lengths)
     n = int(off[-1])
-    assert n > 8192 * nseg  # long enough on average: only the segment count decides
-    say(f"segment pass limit nseg={nseg} n={n}")
-    k = inputs.keys("u32", n, "uniform", seed=nseg)
+    assert n > 8192 * nseg  # the segment passes take it
+    say(f"many long segments nseg={nseg} n={n}")
+    k = inputs.keys("i32", n, "uniform", seed=nseg)
     v = np.arange(n, dtype=np.uint32)
     ko, vo = api.sort_segmented(dev(k), dev(off), dev(v))
     ek, ev = oracle.sort_segmented(k, off, v)
     assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), nseg
+
+
+def test_sort_segmented_many_segments_u64_keys():
+    """64-bit keys (eight passes) over 2,100 segments, key-only, duplicates."""
+    lengths = many_segment_lengths(2100, 140, 7)
+    off = inputs.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    assert n > 8192 * 2100
+    say(f"many long segments u64 n={n}")
+    k = inputs.keys("u64", n, "few", seed=7)
+    assert np.array_equal(host(api.sort_segmented(dev(k), dev(off))), oracle.sort_segmented(k, off))
 
 
 def test_paper_method_small():
