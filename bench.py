@@ -403,8 +403,13 @@ def segments_workload(dev, stream, seed=0):
     tuned = tune.Tuner(cache_path=None, reps=1).tune_segmented(k, toff)
     wall, per = time_steps(lambda: api.sort_segmented(k, toff, keys_out=out, ws=ws), 3, 1, stream)
     ms = sorted(per)[len(per) // 2]
-    res = {"segments": int(lengths.size), "keys": n, "ms_median": round(ms, 3), "seg_blocks": tuned["params"][0],
-           "small_segment_network": bool(tuned["params"][1]),
+    if tune.uses_segment_passes(n, lengths.size):
+        choice = {"path": "segment passes", "pass_threads": tuned["params"][0]}
+    else:
+        choice = {"path": "persistent kernel", "seg_blocks": tuned["params"][0],
+                  "small_segment_network": bool(tuned["params"][1])}
+    res = {"segments": int(lengths.size), "keys": n, "ms_median": round(ms, 3), "tuned": choice,
+           "tuning_trials_ms": tuned["trials"],
            "GKeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
            "GBps_at_36B_per_key": round(n * 36 / (ms * 1e-3) / 1e9, 1)}
     del k, out, ws, toff

@@ -30,6 +30,7 @@ MS_TUNE_PASS_THREADS = 0
 MS_TUNE_SEG_BLOCKS = 1
 MS_TUNE_HIST_BLOCKS = 2
 MS_TUNE_SMALL_SORT = 3
+MS_TUNE_SEG_PASS_THREADS = 4
 
 _lib = None
 _lock = threading.Lock()

@@ -627,22 +627,25 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
 // 5. The digit passes of sort_segmented for long segments: the paper's parts
 // sorted by the whole device at once instead of one workgroup each.
 //
-// Every segment is cut into kTile-key tiles from its own start (its last tile
-// is partial) and the tiles of all segments are numbered in segment order; a
+// Every segment is cut into tiles from its own start (its last tile is
+// partial) and the tiles of all segments are numbered in segment order; a
 // table holds one record per tile.  A tile takes its digit bases from its own
 // segment's histograms, and the segment's first tile publishes INCLUSIVE at
 // once, so that the look-back of every other tile ends inside its segment.  A
 // segment of one tile needs neither histograms nor look-back: its sorted tile
 // is stored in place.  All passes run (no trivial-pass skip): even P
 // ping-pongs keys_in -> workspace -> keys_out -> ... -> keys_out.
+// Tiles of 8,192 keys (512 threads) or, for 32-bit keys without values,
+// 16,384 keys (1,024 threads; a tunable).  The tile size is an argument of
+// the planning kernels and a template parameter of the pass.
 constexpr int kSegSweepThreads = 512;
 // Used when the segments average more keys than one workgroup sorts in LDS
 // (8,192): shorter ones are sorted faster by one workgroup each.
 constexpr uint64_t kSegSweepMinAverage = 8192;
-using SegSweepCfg = PassCfg<kSegSweepThreads>;
+using SegSweepCfg = PassCfg<kSegSweepThreads>;  // the smallest tile: bounds the tile count
 
 // One tile of the segment passes.  `count` holds the tile's key count
-// (1 .. kTile) and two flags.
+// (1 .. tile size) and two flags.
 struct SegTile {
   uint64_t begin;  // index of the tile's first key
   uint32_t count;
@@ -657,21 +660,20 @@ constexpr int kSegPlanThreads = 256;
 constexpr int kSegPlanPerThread = 8;
 constexpr uint32_t kSegChunk = kSegPlanThreads * kSegPlanPerThread;
 
-__device__ __forceinline__ uint32_t segment_tiles(const uint64_t* off, uint64_t s) {
-  constexpr int kTile = SegSweepCfg::kTile;
-  return static_cast<uint32_t>((off[s + 1] - off[s] + kTile - 1) / kTile);
+__device__ __forceinline__ uint32_t segment_tiles(const uint64_t* off, uint64_t s, uint32_t tile) {
+  return static_cast<uint32_t>((off[s + 1] - off[s] + tile - 1) / tile);
 }
 
 // Tiles of this block's segments, each thread summing kSegPlanPerThread
 // consecutive segments; returns the thread's exclusive start inside the block
 // and the block total in *total.
-__device__ __forceinline__ uint32_t chunk_tiles(const uint64_t* off, uint32_t nseg, uint32_t* s_scan,
-                                                uint32_t* total) {
+__device__ __forceinline__ uint32_t chunk_tiles(const uint64_t* off, uint32_t nseg, uint32_t tile,
+                                                uint32_t* s_scan, uint32_t* total) {
   const uint32_t s0 = blockIdx.x * kSegChunk + threadIdx.x * kSegPlanPerThread;
   uint32_t mine = 0;
 #pragma unroll
   for (int i = 0; i < kSegPlanPerThread; ++i)
-    if (s0 + i < nseg) mine += segment_tiles(off, s0 + i);
+    if (s0 + i < nseg) mine += segment_tiles(off, s0 + i, tile);
   const uint32_t start = block_exclusive_scan<kSegPlanThreads>(mine, s_scan);
   __syncthreads();
   if (threadIdx.x == kSegPlanThreads - 1) s_scan[0] = start + mine;
@@ -683,11 +685,11 @@ __device__ __forceinline__ uint32_t chunk_tiles(const uint64_t* off, uint32_t ns
 
 // Plan step 1: tiles per chunk of segments.
 __global__ __launch_bounds__(kSegPlanThreads) void segsweep_count_kernel(const uint64_t* __restrict__ off,
-                                                                        uint32_t nseg,
+                                                                        uint32_t nseg, uint32_t tile,
                                                                         uint32_t* __restrict__ chunk_start) {
   __shared__ uint32_t s_scan[kSegPlanThreads / kWave];
   uint32_t total;
-  chunk_tiles(off, nseg, s_scan, &total);
+  chunk_tiles(off, nseg, tile, s_scan, &total);
   if (threadIdx.x == 0) chunk_start[blockIdx.x] = total;
 }
 
@@ -741,16 +743,15 @@ __global__ __launch_bounds__(1024) void segsweep_plan_kernel(uint32_t* __restric
 // the block (a tile finds its segment by a binary search over the chunk's
 // segment starts in LDS).
 __global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const uint64_t* __restrict__ off,
-                                                                       uint32_t nseg,
+                                                                       uint32_t nseg, uint32_t tile,
                                                                        const uint32_t* __restrict__ chunk_start,
                                                                        SegTile* __restrict__ tiles) {
-  constexpr int kTile = SegSweepCfg::kTile;
   __shared__ uint32_t s_scan[kSegPlanThreads / kWave];
   __shared__ uint32_t s_start[kSegChunk + 1];  // tile start of each segment of the chunk, block-relative
   const uint32_t first_seg = blockIdx.x * kSegChunk;
   const uint32_t nloc = nseg - first_seg < kSegChunk ? nseg - first_seg : kSegChunk;
   uint32_t total;
-  const uint32_t start = chunk_tiles(off, nseg, s_scan, &total);
+  const uint32_t start = chunk_tiles(off, nseg, tile, s_scan, &total);
   {
     const uint32_t l0 = threadIdx.x * kSegPlanPerThread;
     uint32_t run = start;
@@ -758,7 +759,7 @@ __global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const ui
     for (int i = 0; i < kSegPlanPerThread; ++i)
       if (l0 + i < nloc) {
         s_start[l0 + i] = run;
-        run += segment_tiles(off, first_seg + l0 + i);
+        run += segment_tiles(off, first_seg + l0 + i, tile);
       }
     if (threadIdx.x == 0) s_start[nloc] = total;
   }
@@ -777,9 +778,9 @@ __global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const ui
     }
     const uint32_t s = first_seg + lo;
     const uint32_t j = t - s_start[lo];
-    const uint64_t b = off[s] + static_cast<uint64_t>(j) * kTile;
+    const uint64_t b = off[s] + static_cast<uint64_t>(j) * tile;
     const uint64_t e = off[s + 1];
-    const uint32_t cnt = static_cast<uint32_t>(e - b < static_cast<uint64_t>(kTile) ? e - b : kTile);
+    const uint32_t cnt = static_cast<uint32_t>(e - b < static_cast<uint64_t>(tile) ? e - b : tile);
     const bool only = s_start[lo + 1] - s_start[lo] == 1;
     SegTile r;
     r.begin = b;
@@ -853,12 +854,12 @@ __global__ __launch_bounds__(256) void segsweep_hist_kernel(const K* __restrict_
 // segment's digit-p counts.  One block per row; one-tile segments have no
 // histogram and need no bases.
 template <typename C>
-__global__ __launch_bounds__(256) void segsweep_base_kernel(const uint64_t* __restrict__ off, int P,
+__global__ __launch_bounds__(256) void segsweep_base_kernel(const uint64_t* __restrict__ off, int P, uint32_t tile,
                                                             const C* __restrict__ seg_hist, C* __restrict__ seg_base) {
   __shared__ C s_scan[kRadix / kWave];
   const uint32_t row = blockIdx.x;
   const uint64_t s = row / P;
-  if (off[s + 1] - off[s] <= static_cast<uint64_t>(SegSweepCfg::kTile)) return;
+  if (off[s + 1] - off[s] <= tile) return;
   const C c = seg_hist[static_cast<size_t>(row) * kRadix + threadIdx.x];
   C total;
   const C ex = block_exclusive_scan_radix<256>(c, s_scan, &total);
@@ -867,14 +868,14 @@ __global__ __launch_bounds__(256) void segsweep_base_kernel(const uint64_t* __re
 
 // One digit pass over the tiles of every segment (persistent workgroups,
 // tiles by ticket as in onesweep_kernel, without agents or LDS prefetch).
-template <typename K, bool VALS, typename C, typename S>
-__global__ __launch_bounds__(kSegSweepThreads) void segsweep_pass_kernel(
+template <typename K, bool VALS, typename C, typename S, int THREADS>
+__global__ __launch_bounds__(THREADS) void segsweep_pass_kernel(
     const SortPlan* __restrict__ plan, int pass, const SegTile* __restrict__ tiles,
     const uint32_t* __restrict__ num_tiles_p, K flip, const C* __restrict__ seg_base, uint32_t* tile_counter,
     S* status_cur, S* status_next) {
-  constexpr int kThreads = kSegSweepThreads;
-  constexpr int kKpt = SegSweepCfg::kKpt;
-  constexpr int kTile = SegSweepCfg::kTile;
+  constexpr int kThreads = THREADS;
+  constexpr int kKpt = PassCfg<THREADS>::kKpt;
+  constexpr int kTile = PassCfg<THREADS>::kTile;
   constexpr int P = sizeof(K);
   using St = Status<S>;
 
@@ -1260,10 +1261,11 @@ SegSweepLayout segsweep_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64
   return L;
 }
 
-template <typename K, bool VALS, typename C, typename S>
+template <typename K, bool VALS, typename C, typename S, int THREADS>
 ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
                        uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
   constexpr int P = sizeof(K);
+  constexpr uint32_t kTile = PassCfg<THREADS>::kTile;
   SortPlan* plan = reinterpret_cast<SortPlan*>(ws + L.plan);
   uint32_t* ctrs = reinterpret_cast<uint32_t*>(ws + L.ctrs);
   C* hist = reinterpret_cast<C*>(ws + L.hist);
@@ -1276,22 +1278,24 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), L.ctrs_hist_bytes / 16,
             reinterpret_cast<uint4*>(ws + L.status0), L.status_bytes / 16);
   Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
-  MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, chunk_start);
+  MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, kTile,
+            chunk_start);
   MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, 1024, s, chunk_start, L.num_chunks, ctrs, plan,
             buf);
-  MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg,
+  MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, kTile,
             static_cast<const uint32_t*>(chunk_start), records);
   const uint64_t hblocks = std::min<uint64_t>(L.tiles, 2 * device_cus(256));
   MS_LAUNCH("segsweep_hist", (segsweep_hist_kernel<K, C>), static_cast<uint32_t>(hblocks), 256, s,
             static_cast<const K*>(kin), flip, static_cast<const SegTile*>(records), num_tiles, hist);
-  MS_LAUNCH("segsweep_base", segsweep_base_kernel<C>, nseg * P, 256, s, off, P, static_cast<const C*>(hist), base);
+  MS_LAUNCH("segsweep_base", segsweep_base_kernel<C>, nseg * P, 256, s, off, P, kTile, static_cast<const C*>(hist),
+            base);
   const uint64_t blocks = std::min<uint64_t>(
-      L.tiles, resident_blocks(reinterpret_cast<const void*>(&segsweep_pass_kernel<K, VALS, C, S>),
-                               kSegSweepThreads, 256));
+      L.tiles, resident_blocks(reinterpret_cast<const void*>(&segsweep_pass_kernel<K, VALS, C, S, THREADS>),
+                               THREADS, 256));
   for (int p = 0; p < P; ++p) {
     S* next = p + 1 < P ? status[(p + 1) & 1] : nullptr;
-    MS_LAUNCH("segsweep_pass", (segsweep_pass_kernel<K, VALS, C, S>), static_cast<uint32_t>(blocks),
-              kSegSweepThreads, s, static_cast<const SortPlan*>(plan), p, static_cast<const SegTile*>(records),
+    MS_LAUNCH("segsweep_pass", (segsweep_pass_kernel<K, VALS, C, S, THREADS>), static_cast<uint32_t>(blocks),
+              THREADS, s, static_cast<const SortPlan*>(plan), p, static_cast<const SegTile*>(records),
               num_tiles, flip, static_cast<const C*>(base), ctrs + 1 + p, status[p & 1], next);
   }
   return MS_OK;
@@ -1300,8 +1304,17 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
 template <typename K, bool VALS>
 ms_status segsweep_dispatch(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
                             uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
-  if (L.big) return run_segsweep<K, VALS, uint64_t, uint64_t>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
-  return run_segsweep<K, VALS, uint32_t, uint32_t>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+  // 16,384-key tiles only where 1,024 threads fit their registers without
+  // spilling: 32-bit keys without values.
+  if constexpr (sizeof(K) == 4 && !VALS) {
+    if (tune_get(MS_TUNE_SEG_PASS_THREADS) == 1024) {
+      if (L.big)
+        return run_segsweep<K, VALS, uint64_t, uint64_t, 1024>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+      return run_segsweep<K, VALS, uint32_t, uint32_t, 1024>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+    }
+  }
+  if (L.big) return run_segsweep<K, VALS, uint64_t, uint64_t, 512>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+  return run_segsweep<K, VALS, uint32_t, uint32_t, 512>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
 }
 
 }  // namespace

@@ -8,9 +8,12 @@ workload class so later runs start from the known best.
 
 Tuned per class:
   whole-list sorts  digit-pass tile (threads x 16 keys) and histogram grid
-  segmented sorts   persistent workgroup count, and whether segments of at
-                    most 64 keys are ordered by a comparison network
-                    (bitonic, one wave) or by radix passes
+  segmented sorts   segments averaging more than 8,192 keys (whole-device
+                    segment passes): the pass tile (512 or 1,024 threads x
+                    16 keys); shorter ones (persistent kernel): workgroup
+                    count, and whether segments of at most 64 keys are
+                    ordered by a comparison network (bitonic, one wave) or
+                    by radix passes
   serving           the request length above which a request is launched on
                     its own instead of inside a segmented batch
 
@@ -35,7 +38,17 @@ PASS_THREADS = (256, 512, 1024)
 HIST_BLOCKS = (128, 256, 512, 1024)
 SEG_BLOCKS = (256, 512, 1024, 2048)
 SMALL_SORT = (64, 0)
+SEG_PASS_THREADS = (512, 1024)
+# sort_segmented runs whole-device digit passes when there are several
+# segments averaging more than this many keys (mi355sort.h).
+SEG_PASS_MIN_AVERAGE = 8192
 SERVE_THRESHOLDS = (1 << 13, 1 << 16, 1 << 18)
+
+
+def uses_segment_passes(n: int, nseg: int) -> bool:
+    """Whether sort_segmented of n keys in nseg segments takes the
+    whole-device segment passes (else the persistent kernel)."""
+    return nseg > 1 and n > SEG_PASS_MIN_AVERAGE * nseg
 
 
 def size_class(n: int) -> int:
@@ -141,12 +154,18 @@ class Tuner:
         ws = torch.empty(max(1, N.workspace_size(N.MS_OP_SORT_SEGMENTED, kt, vals is not None, n, nseg)),
                          dtype=torch.uint8, device=keys.device)
 
+        def run():
+            api.sort_segmented(keys, offsets, vals, out, vout, ws=ws)
+
+        if uses_segment_passes(n, nseg):
+            def apply_passes(p):
+                N.tune_set(N.MS_TUNE_SEG_PASS_THREADS, p[0])
+
+            return self._search(key + "|passes", [(t,) for t in SEG_PASS_THREADS], apply_passes, run, force)
+
         def apply(p):
             N.tune_set(N.MS_TUNE_SEG_BLOCKS, p[0])
             N.tune_set(N.MS_TUNE_SMALL_SORT, p[1])
-
-        def run():
-            api.sort_segmented(keys, offsets, vals, out, vout, ws=ws)
 
         return self._search(key, list(itertools.product(SEG_BLOCKS, SMALL_SORT)), apply, run, force)
 

@@ -170,6 +170,10 @@ int main(int argc, char** argv) {
     run_segmented<uint64_t>(MS_KEY_U64, {70000, 30001}, true, "few");
     // one-tile segments (stored in place, no histogram) among multi-tile ones
     run_segmented<uint32_t>(MS_KEY_I32, {8192, 1, 0, 30000, 5, 8193, 100, 16385, 7, 40000}, true, "uniform");
+    // 16,384-key tiles (32-bit keys without values)
+    ms_tune_set(MS_TUNE_SEG_PASS_THREADS, 1024);
+    run_segmented<uint32_t>(MS_KEY_I32, {8192, 1, 0, 30000, 5, 16384, 100, 16385, 7, 40000}, false, "uniform");
+    ms_tune_set(MS_TUNE_SEG_PASS_THREADS, 512);
     run_merge<uint32_t>(MS_KEY_U32, {3000, 0, 2500, 1});
     run_merge<uint32_t>(MS_KEY_I32, {20000, 30000, 5, 70000});
     run_merge_split<uint32_t>(MS_KEY_I32, 5 * 4001, 5, true, "few");
@@ -199,6 +203,11 @@ int main(int argc, char** argv) {
     run_segmented<uint32_t>(MS_KEY_I32, {100000}, true, "sorted");
     run_segmented<uint32_t>(MS_KEY_I32, {8192, 1, 0, 30000, 5, 8193, 100, 16385, 7, 40000}, true, "uniform");
     run_segmented<uint64_t>(MS_KEY_U64, {3, 8192, 20000, 8191, 0, 1, 16384, 9000, 2, 30000}, false, "few");
+    ms_tune_set(MS_TUNE_SEG_PASS_THREADS, 1024);
+    run_segmented<uint32_t>(MS_KEY_U32, {16384, 16383, 16385, 8191, 8193, 40000}, false, "small");
+    run_segmented<uint32_t>(MS_KEY_I32, {8192, 1, 0, 30000, 5, 16384, 100, 16385, 7, 40000}, false, "uniform");
+    run_segmented<uint32_t>(MS_KEY_I32, {20000, 30000}, true, "uniform");  // pairs: 8,192-key tiles
+    ms_tune_set(MS_TUNE_SEG_PASS_THREADS, 512);
   }
   if (what == "all" || what == "segmented" || what == "seg") {
     run_segmented<uint32_t>(MS_KEY_I32, {0, 5, 9000, 1, 0, 8192, 8193, 300}, false);

@@ -121,3 +121,24 @@ def test_merge_split_host_side_errors():
     ws = N.workspace_size
     assert ws(N.MS_OP_MERGE_SPLIT, N.MS_KEY_I32, False, 1000, 1) == 0      # one part: a copy
     assert ws(N.MS_OP_MERGE_SPLIT, N.MS_KEY_U64, True, 1000, 4) >= 1000 * 12
+
+
+def test_tune_parameter_checks():
+    """ms_tune_set accepts only the documented values and keeps the old one
+    otherwise (host only)."""
+    lib = N.lib()
+    get = lib.ms_tune_get
+    old = get(N.MS_TUNE_SEG_PASS_THREADS)
+    assert old in (512, 1024)
+    try:
+        for bad in (0, 256, 2048):
+            assert lib.ms_tune_set(N.MS_TUNE_SEG_PASS_THREADS, bad) == N.MS_EINVAL
+            assert get(N.MS_TUNE_SEG_PASS_THREADS) == old
+        assert lib.ms_tune_set(N.MS_TUNE_SEG_PASS_THREADS, 1024) == N.MS_OK
+        assert get(N.MS_TUNE_SEG_PASS_THREADS) == 1024
+    finally:
+        lib.ms_tune_set(N.MS_TUNE_SEG_PASS_THREADS, old)
+    assert lib.ms_tune_set(N.MS_TUNE_PASS_THREADS, 300) == N.MS_EINVAL
+    assert lib.ms_tune_set(N.MS_TUNE_SMALL_SORT, 32) == N.MS_EINVAL
+    assert lib.ms_tune_set(5, 1) == N.MS_EINVAL  # MS_TUNE_COUNT is no parameter
+    assert get(5) == 0

@@ -366,23 +366,34 @@ def many_segment_lengths(nseg, nlong, seed):
     return lengths
 
 
+@pytest.mark.parametrize("threads", [512, 1024])
 @pytest.mark.parametrize("nseg,nlong", [(1025, 60), (2048, 130), (2049, 130), (4700, 320)])
-def test_sort_segmented_many_long_segments(nseg, nlong):
+def test_sort_segmented_many_long_segments(nseg, nlong, threads):
     """Segment passes over thousands of segments: the tile table is planned in
     chunks of 2,048 segments (one, exactly one, just over one and three
     chunks here), one-tile segments are stored in place without histograms,
     the rest take per-segment bases and a look-back that ends at their first
-    tile.  Pairs against the oracle."""
+    tile.  Keys with both pass tiles (16,384-key tiles apply to key-only
+    32-bit sorts), and pairs, against the oracle."""
     lengths = many_segment_lengths(nseg, nlong, nseg)
     off = inputs.offsets_from_lengths(lengths)
     n = int(off[-1])
     assert n > 8192 * nseg  # the segment passes take it
-    say(f"many long segments nseg={nseg} n={n}")
+    say(f"many long segments nseg={nseg} n={n} threads={threads}")
+    from paper_1105_6040_amd import _native as N
     k = inputs.keys("i32", n, "uniform", seed=nseg)
-    v = np.arange(n, dtype=np.uint32)
-    ko, vo = api.sort_segmented(dev(k), dev(off), dev(v))
-    ek, ev = oracle.sort_segmented(k, off, v)
-    assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), nseg
+    old = N.tune_get(N.MS_TUNE_SEG_PASS_THREADS)
+    N.tune_set(N.MS_TUNE_SEG_PASS_THREADS, threads)
+    try:
+        ek = oracle.sort_segmented(k, off)
+        assert np.array_equal(host(api.sort_segmented(dev(k), dev(off))), ek), (nseg, threads)
+        if threads == 512:
+            v = np.arange(n, dtype=np.uint32)
+            ko, vo = api.sort_segmented(dev(k), dev(off), dev(v))
+            ek, ev = oracle.sort_segmented(k, off, v)
+            assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), nseg
+    finally:
+        N.tune_set(N.MS_TUNE_SEG_PASS_THREADS, old)
 
 
 def test_sort_segmented_many_segments_u64_keys():
