@@ -693,30 +693,11 @@ __global__ __launch_bounds__(kSegPlanThreads) void segsweep_count_kernel(const u
   if (threadIdx.x == 0) chunk_start[blockIdx.x] = total;
 }
 
-// Plan step 2 (one block): chunk starts by an exclusive scan of their tile
-// counts, the tile count, and the pass plan.
+// The pass plan of the segment passes (one thread): all P passes run,
+// ping-ponging so that the last one writes keys_out.
 template <typename K, bool VALS>
-__global__ __launch_bounds__(1024) void segsweep_plan_kernel(uint32_t* __restrict__ chunk_start, uint32_t chunks,
-                                                             uint32_t* __restrict__ num_tiles, SortPlan* plan,
-                                                             Buffers buf) {
+__device__ void write_segsweep_plan(SortPlan* plan, const Buffers& buf) {
   constexpr int P = sizeof(K);
-  __shared__ uint32_t s_scan[1024 / kWave];
-  __shared__ uint32_t s_carry;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_carry = 0;
-  __syncthreads();
-  for (uint32_t c0 = 0; c0 < chunks; c0 += 1024) {
-    const uint32_t c = c0 + tid;
-    const uint32_t v = c < chunks ? chunk_start[c] : 0u;
-    const uint32_t ex = block_exclusive_scan<1024>(v, s_scan);
-    const uint32_t carry = s_carry;
-    if (c < chunks) chunk_start[c] = carry + ex;
-    __syncthreads();
-    if (tid == 1023) s_carry = carry + ex + v;
-    __syncthreads();
-  }
-  if (tid != 0) return;
-  *num_tiles = s_carry;
   for (int p = 0; p < kMaxPasses; ++p) {
     PassPlan pp = {};
     if (p < P) {
@@ -739,13 +720,38 @@ __global__ __launch_bounds__(1024) void segsweep_plan_kernel(uint32_t* __restric
   plan->num_active = P;
 }
 
-// Plan step 3: the records of this chunk's tiles, written by all threads of
-// the block (a tile finds its segment by a binary search over the chunk's
-// segment starts in LDS).
-__global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const uint64_t* __restrict__ off,
-                                                                       uint32_t nseg, uint32_t tile,
-                                                                       const uint32_t* __restrict__ chunk_start,
-                                                                       SegTile* __restrict__ tiles) {
+// Plan step 2 (one block): chunk starts by an exclusive scan of their tile
+// counts, the tile count, and the pass plan.
+template <typename K, bool VALS>
+__global__ __launch_bounds__(1024) void segsweep_plan_kernel(uint32_t* __restrict__ chunk_start, uint32_t chunks,
+                                                             uint32_t* __restrict__ num_tiles, SortPlan* plan,
+                                                             Buffers buf) {
+  __shared__ uint32_t s_scan[1024 / kWave];
+  __shared__ uint32_t s_carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (uint32_t c0 = 0; c0 < chunks; c0 += 1024) {
+    const uint32_t c = c0 + tid;
+    const uint32_t v = c < chunks ? chunk_start[c] : 0u;
+    const uint32_t ex = block_exclusive_scan<1024>(v, s_scan);
+    const uint32_t carry = s_carry;
+    if (c < chunks) chunk_start[c] = carry + ex;
+    __syncthreads();
+    if (tid == 1023) s_carry = carry + ex + v;
+    __syncthreads();
+  }
+  if (tid != 0) return;
+  *num_tiles = s_carry;
+  write_segsweep_plan<K, VALS>(plan, buf);
+}
+
+// Plan step 3: the records of this block's chunk of segments, whose first
+// tile is number `base`; written by all threads of the block (a tile finds
+// its segment by a binary search over the chunk's segment starts in LDS).
+// Returns the chunk's tile count.
+__device__ uint32_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, uint32_t tile, uint32_t base,
+                               SegTile* __restrict__ tiles) {
   __shared__ uint32_t s_scan[kSegPlanThreads / kWave];
   __shared__ uint32_t s_start[kSegChunk + 1];  // tile start of each segment of the chunk, block-relative
   const uint32_t first_seg = blockIdx.x * kSegChunk;
@@ -764,7 +770,6 @@ __global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const ui
     if (threadIdx.x == 0) s_start[nloc] = total;
   }
   __syncthreads();
-  const uint32_t base = chunk_start[blockIdx.x];
   for (uint32_t t = threadIdx.x; t < total; t += kSegPlanThreads) {
     // The last local segment whose start is <= t: a non-empty one, since
     // t < its successor's start.
@@ -788,6 +793,28 @@ __global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const ui
     r.seg = s;
     tiles[base + t] = r;
   }
+  return total;
+}
+
+__global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const uint64_t* __restrict__ off,
+                                                                       uint32_t nseg, uint32_t tile,
+                                                                       const uint32_t* __restrict__ chunk_start,
+                                                                       SegTile* __restrict__ tiles) {
+  fill_chunk(off, nseg, tile, chunk_start[blockIdx.x], tiles);
+}
+
+// The whole plan in one launch when the segments form one chunk (at most
+// kSegChunk): records, tile count and pass plan.
+template <typename K, bool VALS>
+__global__ __launch_bounds__(kSegPlanThreads) void segsweep_plan1_kernel(const uint64_t* __restrict__ off,
+                                                                        uint32_t nseg, uint32_t tile,
+                                                                        uint32_t* __restrict__ num_tiles,
+                                                                        SegTile* __restrict__ tiles, SortPlan* plan,
+                                                                        Buffers buf) {
+  const uint32_t total = fill_chunk(off, nseg, tile, 0u, tiles);
+  if (threadIdx.x != 0) return;
+  *num_tiles = total;
+  write_segsweep_plan<K, VALS>(plan, buf);
 }
 
 // Digit histograms of every segment of more than one tile (all P digit
@@ -1278,12 +1305,17 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), L.ctrs_hist_bytes / 16,
             reinterpret_cast<uint4*>(ws + L.status0), L.status_bytes / 16);
   Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
-  MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, kTile,
-            chunk_start);
-  MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, 1024, s, chunk_start, L.num_chunks, ctrs, plan,
-            buf);
-  MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, kTile,
-            static_cast<const uint32_t*>(chunk_start), records);
+  if (L.num_chunks == 1) {
+    MS_LAUNCH("segsweep_plan", (segsweep_plan1_kernel<K, VALS>), 1, kSegPlanThreads, s, off, nseg, kTile, ctrs,
+              records, plan, buf);
+  } else {
+    MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, kTile,
+              chunk_start);
+    MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, 1024, s, chunk_start, L.num_chunks, ctrs, plan,
+              buf);
+    MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, kTile,
+              static_cast<const uint32_t*>(chunk_start), records);
+  }
   const uint64_t hblocks = std::min<uint64_t>(L.tiles, 2 * device_cus(256));
   MS_LAUNCH("segsweep_hist", (segsweep_hist_kernel<K, C>), static_cast<uint32_t>(hblocks), 256, s,
             static_cast<const K*>(kin), flip, static_cast<const SegTile*>(records), num_tiles, hist);

@@ -550,3 +550,49 @@ def test_big_segments_64bit_counters():
         assert torch.equal(out[a:b], torch.sort(k[a:b]).values), s
     del out, k
     torch.cuda.empty_cache()
+
+
+def test_segments_workload_full_size():
+    """The 50,000-segment workload at its full size (lengths log-uniform in
+    [16, 10^6], ~4.56e9 int32 keys, 64-bit counters), as the benchmark runs
+    it.  Over every segment, on the device: keys non-decreasing inside each
+    segment, and per-segment sums of the keys and of a multiplicative hash of
+    them equal to the input's (a permutation inside each segment).  Sampled
+    segments (first, last, longest, ten of one tile, ten longer ones) equal
+    the oracle's sort of the same keys, bit for bit."""
+    lengths = inputs.segment_lengths(0)
+    off = inputs.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    say(f"segments workload full size n={n} nseg={lengths.size}")
+    k = _device_keys(n, 0)
+    toff = dev(off)
+    out = api.sort_segmented(k, toff)
+    torch.cuda.synchronize()
+    say("segments workload: order")
+    ok = out[1:] >= out[:-1]
+    inner = torch.from_numpy(off[1:-1].astype(np.int64) - 1).cuda()
+    inner = inner[(inner >= 0) & (inner < n - 1)]
+    ok[inner] = True  # no order across a segment boundary
+    assert bool(ok.all())
+    del ok
+    say("segments workload: per-segment sums")
+    ends = torch.from_numpy(off.astype(np.int64)).cuda()
+
+    def seg_sums(x):  # wrapping int64 sums over [off[s], off[s+1])
+        c = torch.cumsum(x, 0)
+        before = torch.where(ends > 0, c[(ends - 1).clamp(min=0)], torch.zeros_like(ends))
+        return before[1:] - before[:-1]
+
+    for f in (lambda t: t.to(torch.int64), lambda t: t.to(torch.int64) * -7046029254386353131):
+        assert torch.equal(seg_sums(f(k)), seg_sums(f(out)))
+    say("segments workload: sampled segments against the oracle")
+    g = np.random.default_rng(0)
+    short = np.flatnonzero(lengths <= 8192)
+    longer = np.flatnonzero(lengths > 8192)
+    pick = {0, lengths.size - 1, int(np.argmax(lengths))}
+    pick |= set(g.choice(short, 10, replace=False).tolist()) | set(g.choice(longer, 10, replace=False).tolist())
+    for s in sorted(pick):
+        a, b = int(off[s]), int(off[s + 1])
+        assert np.array_equal(host(out[a:b]), oracle.sort(host(k[a:b]))), s
+    del out, k
+    torch.cuda.empty_cache()
