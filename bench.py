@@ -403,12 +403,14 @@ def segments_workload(dev, stream, seed=0):
     tuned = tune.Tuner(cache_path=None, reps=1).tune_segmented(k, toff)
     wall, per = time_steps(lambda: api.sort_segmented(k, toff, keys_out=out, ws=ws), 3, 1, stream)
     ms = sorted(per)[len(per) // 2]
-    if tune.uses_segment_passes(n, lengths.size):
-        choice = {"path": "segment passes", "pass_threads": tuned["params"][0]}
+    passes, threads, blocks, small = tuned["params"]
+    if passes and tune.uses_segment_passes(n, lengths.size):
+        choice = {"path": "segment passes", "pass_threads": threads}
     else:
-        choice = {"path": "persistent kernel", "seg_blocks": tuned["params"][0],
-                  "small_segment_network": bool(tuned["params"][1])}
+        choice = {"path": "one persistent launch", "seg_blocks": blocks or 1024, "small_segment_network": bool(small)}
+    one_launch = min(t for p, t in tuned["trials"] if p[0] == 0)
     res = {"segments": int(lengths.size), "keys": n, "ms_median": round(ms, 3), "tuned": choice,
+           "one_persistent_launch_best_ms": one_launch,
            "tuning_trials_ms": tuned["trials"],
            "GKeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
            "GBps_at_36B_per_key": round(n * 36 / (ms * 1e-3) / 1e9, 1)}

@@ -98,9 +98,9 @@ ms_status sort_pairs(const void *keys_in, const uint32_t *vals_in, void *keys_ou
  * own (no item crosses a segment boundary; empty segments are allowed).
  * vals_in / vals_out may both be NULL for a key-only sort.  In-place is
  * allowed under the same rule as sort_pairs.  Several segments averaging more
- * than 8,192 keys are sorted by whole-device digit passes over all of them,
- * shorter ones by workgroups that each take whole segments; the result is
- * the same.  num_segments = 0 requires
+ * than 8,192 keys are sorted by whole-device digit passes over all of them
+ * (unless MS_TUNE_SEG_PASSES is 0), other calls by one launch of a persistent
+ * kernel whose workgroups each take whole segments; the result is the same.  num_segments = 0 requires
  * n_total = 0.  Errors: MS_EINVAL for NULL pointers with n_total > 0, a NULL
  * offsets array with num_segments > 0, num_segments = 0 with n_total > 0, a
  * short workspace, or only one of vals_in / vals_out given.
@@ -172,6 +172,11 @@ const char *ms_last_error(void);
  *                         of 8,192 / 16,384 keys).  Default 512.  1024
  *                         applies to 32-bit keys without values; other
  *                         sorts use 512.
+ *   MS_TUNE_SEG_PASSES    1 (the default): sort_segmented runs whole-device
+ *                         digit passes when the segments average more than
+ *                         8,192 keys; 0: every sort_segmented call is one
+ *                         launch of the persistent kernel, whose workgroups
+ *                         each take whole segments.
  * ms_tune_set returns MS_EINVAL for an unknown parameter or value;
  * ms_tune_get returns the current value (0 for an unknown parameter).
  */
@@ -181,7 +186,8 @@ typedef enum ms_tune_param {
     MS_TUNE_HIST_BLOCKS = 2,
     MS_TUNE_SMALL_SORT = 3,
     MS_TUNE_SEG_PASS_THREADS = 4,
-    MS_TUNE_COUNT = 5
+    MS_TUNE_SEG_PASSES = 5,
+    MS_TUNE_COUNT = 6
 } ms_tune_param;
 
 ms_status ms_tune_set(ms_tune_param param, int64_t value);

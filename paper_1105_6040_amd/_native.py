@@ -31,6 +31,7 @@ MS_TUNE_SEG_BLOCKS = 1
 MS_TUNE_HIST_BLOCKS = 2
 MS_TUNE_SMALL_SORT = 3
 MS_TUNE_SEG_PASS_THREADS = 4
+MS_TUNE_SEG_PASSES = 5
 
 _lib = None
 _lock = threading.Lock()

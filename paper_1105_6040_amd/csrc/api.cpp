@@ -34,7 +34,7 @@ std::mutex g_timing_mu;
 
 bool valid_kt(ms_key_type kt) { return kt == MS_KEY_I32 || kt == MS_KEY_U32 || kt == MS_KEY_U64; }
 
-std::atomic<int64_t> g_tune[MS_TUNE_COUNT] = {{1024}, {0}, {0}, {64}, {512}};
+std::atomic<int64_t> g_tune[MS_TUNE_COUNT] = {{1024}, {0}, {0}, {64}, {512}, {1}};
 }  // namespace
 
 int64_t tune_get(ms_tune_param p) { return (p >= 0 && p < MS_TUNE_COUNT) ? g_tune[p].load() : 0; }
@@ -211,6 +211,11 @@ ms_status ms_tune_set(ms_tune_param p, int64_t value) {
     case MS_TUNE_SMALL_SORT:
       if (value != 0 && value != 64)
         return fail(MS_EINVAL, "MS_TUNE_SMALL_SORT must be 0 or 64 (got %lld)", static_cast<long long>(value));
+      ms::g_tune[p] = value;
+      return MS_OK;
+    case MS_TUNE_SEG_PASSES:
+      if (value != 0 && value != 1)
+        return fail(MS_EINVAL, "MS_TUNE_SEG_PASSES must be 0 or 1 (got %lld)", static_cast<long long>(value));
       ms::g_tune[p] = value;
       return MS_OK;
     case MS_TUNE_SEG_PASS_THREADS:

@@ -20,6 +20,8 @@
 //      tile, reordering each tile in LDS and writing its digit runs at
 //      running per-digit offsets kept in LDS.  One workgroup owns the
 //      segment, so no cross-workgroup look-back is needed.
+#include <algorithm>
+
 #include "ms_device.hpp"
 #include "ms_runtime.hpp"
 #include "ms_tile.hpp"
@@ -484,8 +486,10 @@ ms_status run_segmented(const void* kin, const uint32_t* vin, void* kout, uint32
 
 size_t segmented_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg) {
   if (nseg == 1) return radix_workspace_bytes(kt, has_vals, n);
-  if (segsweep_eligible(n, nseg)) return segsweep_workspace_bytes(kt, has_vals, n, nseg);
-  return seg_layout(kt, has_vals, n, nseg).total;
+  const size_t persistent = seg_layout(kt, has_vals, n, nseg).total;
+  // Either path may run (MS_TUNE_SEG_PASSES), so the workspace covers both.
+  if (segsweep_eligible(n, nseg)) return std::max(persistent, segsweep_workspace_bytes(kt, has_vals, n, nseg));
+  return persistent;
 }
 
 ms_status segmented_sort(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
@@ -495,8 +499,9 @@ ms_status segmented_sort(const void* keys_in, const uint32_t* vals_in, void* key
   // whole-list sort.
   if (nseg == 1) return radix_sort(keys_in, vals_in, keys_out, vals_out, n, kt, ws, ws_bytes, s);
   // Long segments (more than 8,192 keys on average): whole-device digit
-  // passes over all of them (the host knows only the counts, which decide).
-  if (segsweep_eligible(n, nseg))
+  // passes over all of them (the host knows only the counts, which decide),
+  // unless the caller asked for the one-launch persistent kernel.
+  if (tune_get(MS_TUNE_SEG_PASSES) && segsweep_eligible(n, nseg))
     return segsweep_sort(keys_in, vals_in, keys_out, vals_out, offsets, nseg, n, kt, ws, ws_bytes, s);
   const bool vals = vals_in != nullptr;
   const SegLayout L = seg_layout(kt, vals, n, nseg);

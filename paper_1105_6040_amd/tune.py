@@ -8,12 +8,12 @@ workload class so later runs start from the known best.
 
 Tuned per class:
   whole-list sorts  digit-pass tile (threads x 16 keys) and histogram grid
-  segmented sorts   segments averaging more than 8,192 keys (whole-device
-                    segment passes): the pass tile (512 or 1,024 threads x
-                    16 keys); shorter ones (persistent kernel): workgroup
-                    count, and whether segments of at most 64 keys are
-                    ordered by a comparison network (bitonic, one wave) or
-                    by radix passes
+  segmented sorts   the one-launch persistent kernel (workgroup count, and
+                    whether segments of at most 64 keys are ordered by a
+                    comparison network -- bitonic, one wave -- or by radix
+                    passes) and, for segments averaging more than 8,192
+                    keys, the whole-device segment passes (pass tile: 512
+                    or 1,024 threads x 16 keys) as further candidates
   serving           the request length above which a request is launched on
                     its own instead of inside a segmented batch
 
@@ -157,17 +157,19 @@ class Tuner:
         def run():
             api.sort_segmented(keys, offsets, vals, out, vout, ws=ws)
 
+        # (segment passes on, pass threads, persistent workgroups, small-segment network)
+        persistent = [(0, SEG_PASS_THREADS[0], b, m) for b, m in itertools.product(SEG_BLOCKS, SMALL_SORT)]
+        space = persistent
         if uses_segment_passes(n, nseg):
-            def apply_passes(p):
-                N.tune_set(N.MS_TUNE_SEG_PASS_THREADS, p[0])
-
-            return self._search(key + "|passes", [(t,) for t in SEG_PASS_THREADS], apply_passes, run, force)
+            space = [(1, t, 0, SMALL_SORT[0]) for t in SEG_PASS_THREADS] + persistent
 
         def apply(p):
-            N.tune_set(N.MS_TUNE_SEG_BLOCKS, p[0])
-            N.tune_set(N.MS_TUNE_SMALL_SORT, p[1])
+            N.tune_set(N.MS_TUNE_SEG_PASSES, p[0])
+            N.tune_set(N.MS_TUNE_SEG_PASS_THREADS, p[1])
+            N.tune_set(N.MS_TUNE_SEG_BLOCKS, p[2])
+            N.tune_set(N.MS_TUNE_SMALL_SORT, p[3])
 
-        return self._search(key, list(itertools.product(SEG_BLOCKS, SMALL_SORT)), apply, run, force)
+        return self._search(key + "|v2", space, apply, run, force)
 
     def tune_serving(self, run_server: Callable[[int], "object"], force: bool = False,
                      thresholds: Iterable[int] = SERVE_THRESHOLDS) -> dict:

@@ -140,5 +140,9 @@ def test_tune_parameter_checks():
         lib.ms_tune_set(N.MS_TUNE_SEG_PASS_THREADS, old)
     assert lib.ms_tune_set(N.MS_TUNE_PASS_THREADS, 300) == N.MS_EINVAL
     assert lib.ms_tune_set(N.MS_TUNE_SMALL_SORT, 32) == N.MS_EINVAL
-    assert lib.ms_tune_set(5, 1) == N.MS_EINVAL  # MS_TUNE_COUNT is no parameter
-    assert get(5) == 0
+    old = get(N.MS_TUNE_SEG_PASSES)
+    assert old in (0, 1)
+    assert lib.ms_tune_set(N.MS_TUNE_SEG_PASSES, 2) == N.MS_EINVAL
+    assert get(N.MS_TUNE_SEG_PASSES) == old
+    assert lib.ms_tune_set(6, 1) == N.MS_EINVAL  # MS_TUNE_COUNT is no parameter
+    assert get(6) == 0

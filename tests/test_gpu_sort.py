@@ -396,6 +396,30 @@ def test_sort_segmented_many_long_segments(nseg, nlong, threads):
         N.tune_set(N.MS_TUNE_SEG_PASS_THREADS, old)
 
 
+@pytest.mark.parametrize("nseg,nlong", [(1025, 60), (2049, 130)])
+def test_sort_segmented_one_launch_for_long_segments(nseg, nlong):
+    """With MS_TUNE_SEG_PASSES = 0 segments averaging > 8,192 keys take the
+    one-launch persistent kernel instead of the segment passes: keys and
+    pairs against the oracle."""
+    from paper_1105_6040_amd import _native as N
+    lengths = many_segment_lengths(nseg, nlong, nseg + 1)
+    off = inputs.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    assert n > 8192 * nseg
+    say(f"one launch for long segments nseg={nseg} n={n}")
+    k = inputs.keys("i32", n, "uniform", seed=nseg + 1)
+    v = np.arange(n, dtype=np.uint32)
+    old = N.tune_get(N.MS_TUNE_SEG_PASSES)
+    N.tune_set(N.MS_TUNE_SEG_PASSES, 0)
+    try:
+        assert np.array_equal(host(api.sort_segmented(dev(k), dev(off))), oracle.sort_segmented(k, off)), nseg
+        ko, vo = api.sort_segmented(dev(k), dev(off), dev(v))
+        ek, ev = oracle.sort_segmented(k, off, v)
+        assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), nseg
+    finally:
+        N.tune_set(N.MS_TUNE_SEG_PASSES, old)
+
+
 def test_sort_segmented_many_segments_u64_keys():
     """64-bit keys (eight passes) over 2,100 segments, key-only, duplicates."""
     lengths = many_segment_lengths(2100, 140, 7)
@@ -594,5 +618,13 @@ def test_segments_workload_full_size():
     for s in sorted(pick):
         a, b = int(off[s]), int(off[s + 1])
         assert np.array_equal(host(out[a:b]), oracle.sort(host(k[a:b]))), s
+    say("segments workload: the one-launch persistent kernel gives the same result")
+    from paper_1105_6040_amd import _native as N
+    old = N.tune_get(N.MS_TUNE_SEG_PASSES)
+    N.tune_set(N.MS_TUNE_SEG_PASSES, 0)
+    try:
+        assert torch.equal(api.sort_segmented(k, toff), out)
+    finally:
+        N.tune_set(N.MS_TUNE_SEG_PASSES, old)
     del out, k
     torch.cuda.empty_cache()
