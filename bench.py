@@ -293,6 +293,31 @@ def extra_workloads(args, dev, stream, keys_u, keys_u_np):
                             "us_p99": round(percentile(per, 99) * 1e3, 1)}
     # The paper's method (parts sorted, then merged) must give the whole-list sort.
     assert torch.equal(m_out, api.sort_keys(k)), "paper method differs from sort_keys"
+    # The same two calls captured once in a HIP graph and replayed back to back
+    # (no allocation, memset or host wait inside a call, so they capture).
+    ws_s = torch.empty(max(1, N.workspace_size(N.MS_OP_SORT_SEGMENTED, N.MS_KEY_I32, False, k.numel(), p)),
+                       dtype=torch.uint8, device=dev)
+    ws_m = torch.empty(max(1, N.workspace_size(N.MS_OP_MERGE_RUNS, N.MS_KEY_I32, False, k.numel(), p)),
+                       dtype=torch.uint8, device=dev)
+
+    def paper_ws():
+        api.sort_segmented(k, toff, keys_out=s_out, ws=ws_s)
+        api.merge_runs(s_out, toff, keys_out=m_out, ws=ws_m)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        paper_ws()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        paper_ws()
+    m_out.zero_()
+    wall_g, per_g = time_steps(graph.replay, 100, 10, stream)
+    assert torch.equal(m_out, api.sort_keys(k)), "graph replay of the paper method differs from sort_keys"
+    ex["paper_small_p4"]["graph_replay_us_median"] = round(sorted(per_g)[len(per_g) // 2] * 1e3, 1)
+    ex["paper_small_p4"]["graph_replay_us_p99"] = round(percentile(per_g, 99) * 1e3, 1)
+    del graph, ws_s, ws_m
     del k, toff, s_out, m_out
 
     ex["segments_50k"] = segments_workload(dev, stream)
