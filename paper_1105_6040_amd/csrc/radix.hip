@@ -660,20 +660,32 @@ constexpr int kSegPlanThreads = 256;
 constexpr int kSegPlanPerThread = 8;
 constexpr uint32_t kSegChunk = kSegPlanThreads * kSegPlanPerThread;
 
-__device__ __forceinline__ uint32_t segment_tiles(const uint64_t* off, uint64_t s, uint32_t tile) {
-  return static_cast<uint32_t>((off[s + 1] - off[s] + tile - 1) / tile);
+// Segment s as [*begin, *begin + length): offsets clamped to n, a decreasing
+// pair read as empty, so that offsets that break the contract never lead
+// outside [0, n).
+__device__ __forceinline__ uint64_t segment_span(const uint64_t* off, uint64_t s, uint64_t n, uint64_t* begin) {
+  uint64_t b = off[s], e = off[s + 1];
+  b = b < n ? b : n;
+  e = e < n ? e : n;
+  *begin = b;
+  return e > b ? e - b : 0;
+}
+
+__device__ __forceinline__ uint32_t segment_tiles(const uint64_t* off, uint64_t s, uint64_t n, uint32_t tile) {
+  uint64_t b;
+  return static_cast<uint32_t>((segment_span(off, s, n, &b) + tile - 1) / tile);
 }
 
 // Tiles of this block's segments, each thread summing kSegPlanPerThread
 // consecutive segments; returns the thread's exclusive start inside the block
 // and the block total in *total.
-__device__ __forceinline__ uint32_t chunk_tiles(const uint64_t* off, uint32_t nseg, uint32_t tile,
+__device__ __forceinline__ uint32_t chunk_tiles(const uint64_t* off, uint32_t nseg, uint64_t n, uint32_t tile,
                                                 uint32_t* s_scan, uint32_t* total) {
   const uint32_t s0 = blockIdx.x * kSegChunk + threadIdx.x * kSegPlanPerThread;
   uint32_t mine = 0;
 #pragma unroll
   for (int i = 0; i < kSegPlanPerThread; ++i)
-    if (s0 + i < nseg) mine += segment_tiles(off, s0 + i, tile);
+    if (s0 + i < nseg) mine += segment_tiles(off, s0 + i, n, tile);
   const uint32_t start = block_exclusive_scan<kSegPlanThreads>(mine, s_scan);
   __syncthreads();
   if (threadIdx.x == kSegPlanThreads - 1) s_scan[0] = start + mine;
@@ -685,11 +697,11 @@ __device__ __forceinline__ uint32_t chunk_tiles(const uint64_t* off, uint32_t ns
 
 // Plan step 1: tiles per chunk of segments.
 __global__ __launch_bounds__(kSegPlanThreads) void segsweep_count_kernel(const uint64_t* __restrict__ off,
-                                                                        uint32_t nseg, uint32_t tile,
+                                                                        uint32_t nseg, uint64_t n, uint32_t tile,
                                                                         uint32_t* __restrict__ chunk_start) {
   __shared__ uint32_t s_scan[kSegPlanThreads / kWave];
   uint32_t total;
-  chunk_tiles(off, nseg, tile, s_scan, &total);
+  chunk_tiles(off, nseg, n, tile, s_scan, &total);
   if (threadIdx.x == 0) chunk_start[blockIdx.x] = total;
 }
 
@@ -724,8 +736,8 @@ __device__ void write_segsweep_plan(SortPlan* plan, const Buffers& buf) {
 // counts, the tile count, and the pass plan.
 template <typename K, bool VALS>
 __global__ __launch_bounds__(1024) void segsweep_plan_kernel(uint32_t* __restrict__ chunk_start, uint32_t chunks,
-                                                             uint32_t* __restrict__ num_tiles, SortPlan* plan,
-                                                             Buffers buf) {
+                                                             uint32_t max_tiles, uint32_t* __restrict__ num_tiles,
+                                                             SortPlan* plan, Buffers buf) {
   __shared__ uint32_t s_scan[1024 / kWave];
   __shared__ uint32_t s_carry;
   const int tid = threadIdx.x;
@@ -742,22 +754,26 @@ __global__ __launch_bounds__(1024) void segsweep_plan_kernel(uint32_t* __restric
     __syncthreads();
   }
   if (tid != 0) return;
-  *num_tiles = s_carry;
+  // Offsets within the contract give at most max_tiles tiles (the size of
+  // the record and status tables); overlapping ones may give more, which
+  // are dropped.
+  *num_tiles = s_carry < max_tiles ? s_carry : max_tiles;
   write_segsweep_plan<K, VALS>(plan, buf);
 }
 
 // Plan step 3: the records of this block's chunk of segments, whose first
 // tile is number `base`; written by all threads of the block (a tile finds
 // its segment by a binary search over the chunk's segment starts in LDS).
-// Returns the chunk's tile count.
-__device__ uint32_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, uint32_t tile, uint32_t base,
-                               SegTile* __restrict__ tiles) {
+// Returns the chunk's tile count; records from max_tiles on are not written.
+__device__ uint32_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, uint64_t n, uint32_t tile,
+                               uint32_t base, uint32_t max_tiles, SegTile* __restrict__ tiles) {
   __shared__ uint32_t s_scan[kSegPlanThreads / kWave];
   __shared__ uint32_t s_start[kSegChunk + 1];  // tile start of each segment of the chunk, block-relative
+  __shared__ uint64_t s_off[kSegChunk + 1];    // the chunk's offsets, clamped to n
   const uint32_t first_seg = blockIdx.x * kSegChunk;
   const uint32_t nloc = nseg - first_seg < kSegChunk ? nseg - first_seg : kSegChunk;
   uint32_t total;
-  const uint32_t start = chunk_tiles(off, nseg, tile, s_scan, &total);
+  const uint32_t start = chunk_tiles(off, nseg, n, tile, s_scan, &total);
   {
     const uint32_t l0 = threadIdx.x * kSegPlanPerThread;
     uint32_t run = start;
@@ -765,12 +781,18 @@ __device__ uint32_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, 
     for (int i = 0; i < kSegPlanPerThread; ++i)
       if (l0 + i < nloc) {
         s_start[l0 + i] = run;
-        run += segment_tiles(off, first_seg + l0 + i, tile);
+        run += segment_tiles(off, first_seg + l0 + i, n, tile);
       }
     if (threadIdx.x == 0) s_start[nloc] = total;
+    for (uint32_t i = threadIdx.x; i <= nloc; i += kSegPlanThreads) {
+      const uint64_t v = off[first_seg + i];
+      s_off[i] = v < n ? v : n;
+    }
   }
   __syncthreads();
-  for (uint32_t t = threadIdx.x; t < total; t += kSegPlanThreads) {
+  const uint32_t room = base < max_tiles ? max_tiles - base : 0u;
+  const uint32_t end = total < room ? total : room;
+  for (uint32_t t = threadIdx.x; t < end; t += kSegPlanThreads) {
     // The last local segment whose start is <= t: a non-empty one, since
     // t < its successor's start.
     uint32_t lo = 0, hi = nloc;
@@ -783,8 +805,9 @@ __device__ uint32_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, 
     }
     const uint32_t s = first_seg + lo;
     const uint32_t j = t - s_start[lo];
-    const uint64_t b = off[s] + static_cast<uint64_t>(j) * tile;
-    const uint64_t e = off[s + 1];
+    const uint64_t sb = s_off[lo], se = s_off[lo + 1] > sb ? s_off[lo + 1] : sb;  // as segment_span
+    const uint64_t b = sb + static_cast<uint64_t>(j) * tile;
+    const uint64_t e = se;
     const uint32_t cnt = static_cast<uint32_t>(e - b < static_cast<uint64_t>(tile) ? e - b : tile);
     const bool only = s_start[lo + 1] - s_start[lo] == 1;
     SegTile r;
@@ -797,23 +820,25 @@ __device__ uint32_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, 
 }
 
 __global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const uint64_t* __restrict__ off,
-                                                                       uint32_t nseg, uint32_t tile,
+                                                                       uint32_t nseg, uint64_t n, uint32_t tile,
                                                                        const uint32_t* __restrict__ chunk_start,
+                                                                       uint32_t max_tiles,
                                                                        SegTile* __restrict__ tiles) {
-  fill_chunk(off, nseg, tile, chunk_start[blockIdx.x], tiles);
+  fill_chunk(off, nseg, n, tile, chunk_start[blockIdx.x], max_tiles, tiles);
 }
 
 // The whole plan in one launch when the segments form one chunk (at most
 // kSegChunk): records, tile count and pass plan.
 template <typename K, bool VALS>
 __global__ __launch_bounds__(kSegPlanThreads) void segsweep_plan1_kernel(const uint64_t* __restrict__ off,
-                                                                        uint32_t nseg, uint32_t tile,
+                                                                        uint32_t nseg, uint64_t n, uint32_t tile,
+                                                                        uint32_t max_tiles,
                                                                         uint32_t* __restrict__ num_tiles,
                                                                         SegTile* __restrict__ tiles, SortPlan* plan,
                                                                         Buffers buf) {
-  const uint32_t total = fill_chunk(off, nseg, tile, 0u, tiles);
+  const uint32_t total = fill_chunk(off, nseg, n, tile, 0u, max_tiles, tiles);
   if (threadIdx.x != 0) return;
-  *num_tiles = total;
+  *num_tiles = total < max_tiles ? total : max_tiles;
   write_segsweep_plan<K, VALS>(plan, buf);
 }
 
@@ -881,16 +906,18 @@ __global__ __launch_bounds__(256) void segsweep_hist_kernel(const K* __restrict_
 // segment's digit-p counts.  One block per row; one-tile segments have no
 // histogram and need no bases.
 template <typename C>
-__global__ __launch_bounds__(256) void segsweep_base_kernel(const uint64_t* __restrict__ off, int P, uint32_t tile,
-                                                            const C* __restrict__ seg_hist, C* __restrict__ seg_base) {
+__global__ __launch_bounds__(256) void segsweep_base_kernel(const uint64_t* __restrict__ off, uint64_t n, int P,
+                                                            uint32_t tile, const C* __restrict__ seg_hist,
+                                                            C* __restrict__ seg_base) {
   __shared__ C s_scan[kRadix / kWave];
   const uint32_t row = blockIdx.x;
   const uint64_t s = row / P;
-  if (off[s + 1] - off[s] <= tile) return;
+  uint64_t b;
+  if (segment_span(off, s, n, &b) <= tile) return;
   const C c = seg_hist[static_cast<size_t>(row) * kRadix + threadIdx.x];
   C total;
   const C ex = block_exclusive_scan_radix<256>(c, s_scan, &total);
-  seg_base[static_cast<size_t>(row) * kRadix + threadIdx.x] = static_cast<C>(off[s]) + ex;
+  seg_base[static_cast<size_t>(row) * kRadix + threadIdx.x] = static_cast<C>(b) + ex;
 }
 
 // One digit pass over the tiles of every segment (persistent workgroups,
@@ -898,7 +925,7 @@ __global__ __launch_bounds__(256) void segsweep_base_kernel(const uint64_t* __re
 template <typename K, bool VALS, typename C, typename S, int THREADS>
 __global__ __launch_bounds__(THREADS) void segsweep_pass_kernel(
     const SortPlan* __restrict__ plan, int pass, const SegTile* __restrict__ tiles,
-    const uint32_t* __restrict__ num_tiles_p, K flip, const C* __restrict__ seg_base, uint32_t* tile_counter,
+    const uint32_t* __restrict__ num_tiles_p, C n, K flip, const C* __restrict__ seg_base, uint32_t* tile_counter,
     S* status_cur, S* status_next) {
   constexpr int kThreads = THREADS;
   constexpr int kKpt = PassCfg<THREADS>::kKpt;
@@ -1018,10 +1045,15 @@ __global__ __launch_bounds__(THREADS) void segsweep_pass_kernel(
 
     const C remaining = cur_end - cur_base;
     const int valid = remaining < static_cast<C>(kTile) ? static_cast<int>(remaining) : kTile;
+    // Destinations lie inside the tile's segment whenever the offsets keep
+    // the contract; the clamp (a branch here costs ~10 % of the pass) keeps
+    // overlapping segments, whose keys other tiles rewrite between passes,
+    // inside the array.
 #pragma unroll 4
     for (int i = tid; i < valid; i += kThreads) {
       const K k = s_stage[pad16(i)];
-      const C o = s_doff[digit_of(k, shift)] + static_cast<C>(i);
+      C o = s_doff[digit_of(k, shift)] + static_cast<C>(i);
+      o = o < n ? o : n - 1;
       dst[o] = k ^ out_flip;
       if constexpr (VALS) dst_v[o] = s_vstage[pad16(i)];
     }
@@ -1305,22 +1337,23 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), L.ctrs_hist_bytes / 16,
             reinterpret_cast<uint4*>(ws + L.status0), L.status_bytes / 16);
   Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
+  const uint32_t max_tiles = static_cast<uint32_t>(L.tiles);
   if (L.num_chunks == 1) {
-    MS_LAUNCH("segsweep_plan", (segsweep_plan1_kernel<K, VALS>), 1, kSegPlanThreads, s, off, nseg, kTile, ctrs,
-              records, plan, buf);
+    MS_LAUNCH("segsweep_plan", (segsweep_plan1_kernel<K, VALS>), 1, kSegPlanThreads, s, off, nseg, n, kTile,
+              max_tiles, ctrs, records, plan, buf);
   } else {
-    MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, kTile,
+    MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile,
               chunk_start);
-    MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, 1024, s, chunk_start, L.num_chunks, ctrs, plan,
-              buf);
-    MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, kTile,
-              static_cast<const uint32_t*>(chunk_start), records);
+    MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, 1024, s, chunk_start, L.num_chunks, max_tiles,
+              ctrs, plan, buf);
+    MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile,
+              static_cast<const uint32_t*>(chunk_start), max_tiles, records);
   }
   const uint64_t hblocks = std::min<uint64_t>(L.tiles, 2 * device_cus(256));
   MS_LAUNCH("segsweep_hist", (segsweep_hist_kernel<K, C>), static_cast<uint32_t>(hblocks), 256, s,
             static_cast<const K*>(kin), flip, static_cast<const SegTile*>(records), num_tiles, hist);
-  MS_LAUNCH("segsweep_base", segsweep_base_kernel<C>, nseg * P, 256, s, off, P, kTile, static_cast<const C*>(hist),
-            base);
+  MS_LAUNCH("segsweep_base", segsweep_base_kernel<C>, nseg * P, 256, s, off, n, P, kTile,
+            static_cast<const C*>(hist), base);
   const uint64_t blocks = std::min<uint64_t>(
       L.tiles, resident_blocks(reinterpret_cast<const void*>(&segsweep_pass_kernel<K, VALS, C, S, THREADS>),
                                THREADS, 256));
@@ -1328,7 +1361,7 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
     S* next = p + 1 < P ? status[(p + 1) & 1] : nullptr;
     MS_LAUNCH("segsweep_pass", (segsweep_pass_kernel<K, VALS, C, S, THREADS>), static_cast<uint32_t>(blocks),
               THREADS, s, static_cast<const SortPlan*>(plan), p, static_cast<const SegTile*>(records),
-              num_tiles, flip, static_cast<const C*>(base), ctrs + 1 + p, status[p & 1], next);
+              num_tiles, static_cast<C>(n), flip, static_cast<const C*>(base), ctrs + 1 + p, status[p & 1], next);
   }
   return MS_OK;
 }
@@ -1381,7 +1414,9 @@ bool segsweep_eligible(uint64_t n, uint64_t nseg) {
   // per (segment, digit position) in one grid dimension.
   if (nseg < 1 || nseg * kMaxPasses >= (1ull << 31)) return false;
   const uint64_t tiles = (n + SegSweepCfg::kTile - 1) / SegSweepCfg::kTile + nseg;
-  return n > kSegSweepMinAverage * nseg && tiles < (1ull << 32);
+  // Segments averaging more than a tile, or any call of 2^32 keys or more
+  // (the other path counts a segment's keys in 32 bits).
+  return (n > kSegSweepMinAverage * nseg || n >= (1ull << 32)) && tiles < (1ull << 32);
 }
 
 size_t segsweep_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg) {

@@ -395,11 +395,15 @@ __global__ __launch_bounds__(THREADS, (seg_min_waves_per_simd<K, VALS>())) void 
         const uint32_t start = block_exclusive_scan_radix<THREADS>(cnt, s_cscan, &tile_total);
         if (tid < kRadix) s_doff[tid] = s_run[tid] - start;
         lds_barrier();
+        // Destinations stay inside the segment whenever the offsets keep the
+        // contract; the clamp keeps overlapping segments (rewritten by other
+        // workgroups between passes) inside their own range.
         for (int i = tid; i < valid; i += THREADS) {
           const K k = s_stage[pad16(i)];
-          const uint64_t o = begin + static_cast<uint32_t>(s_doff[digit_of(k, shift)] + static_cast<uint32_t>(i));
-          dst[o] = k ^ out_flip;
-          if constexpr (VALS) dstv[o] = s_vstage[pad16(i)];
+          uint64_t rel = static_cast<uint32_t>(s_doff[digit_of(k, shift)] + static_cast<uint32_t>(i));
+          rel = rel < len ? rel : len - 1;
+          dst[begin + rel] = k ^ out_flip;
+          if constexpr (VALS) dstv[begin + rel] = s_vstage[pad16(i)];
         }
         lds_barrier();
         if (tid < kRadix) s_run[tid] += cnt;
@@ -500,7 +504,9 @@ ms_status segmented_sort(const void* keys_in, const uint32_t* vals_in, void* key
   if (nseg == 1) return radix_sort(keys_in, vals_in, keys_out, vals_out, n, kt, ws, ws_bytes, s);
   // Long segments (more than 8,192 keys on average): whole-device digit
   // passes over all of them (the host knows only the counts, which decide),
-  // unless the caller asked for the one-launch persistent kernel.
+  // and any call of 2^32 keys or more (this kernel counts a segment's keys
+  // in 32 bits), unless the caller asked for the one-launch persistent
+  // kernel.
   if (tune_get(MS_TUNE_SEG_PASSES) && segsweep_eligible(n, nseg))
     return segsweep_sort(keys_in, vals_in, keys_out, vals_out, offsets, nseg, n, kt, ws, ws_bytes, s);
   const bool vals = vals_in != nullptr;

@@ -100,6 +100,32 @@ static void run_segmented(int kt, const std::vector<uint64_t>& lengths, bool pai
   if (!ok) ++failures;
 }
 
+// Offsets that break the contract (decreasing pairs, overlapping segments,
+// entries beyond n): the order is unspecified, but the call must succeed and
+// every access stay inside the buffers (buffers and workspace are sized
+// exactly, so AddressSanitizer sees any access past them).
+template <typename K>
+static void run_malformed(int kt, const std::vector<uint64_t>& off, size_t n, bool pairs, int seg_passes) {
+  std::vector<uint64_t> bits;
+  fill(bits, kt, n, "uniform");
+  std::vector<K> kin = narrow<K>(bits), kout(n);
+  std::vector<uint32_t> vin(n), vout(n);
+  for (size_t i = 0; i < n; ++i) vin[i] = static_cast<uint32_t>(i);
+  const uint64_t nseg = off.size() - 1;
+  size_t wsb = 0;
+  ms_workspace_size(MS_OP_SORT_SEGMENTED, (ms_key_type)kt, pairs, n, nseg, &wsb);
+  std::vector<char> ws(wsb);
+  ms_tune_set(MS_TUNE_SEG_PASSES, seg_passes);
+  ms_status st = sort_segmented(kin.data(), pairs ? vin.data() : nullptr, kout.data(), pairs ? vout.data() : nullptr,
+                                off.data(), nseg, n, (ms_key_type)kt, ws.data(), wsb, nullptr);
+  ms_tune_set(MS_TUNE_SEG_PASSES, 1);
+  const bool ok = st == MS_OK;
+  printf("%s sort_segmented malformed offsets kt=%d nseg=%llu n=%zu pairs=%d seg_passes=%d\n", ok ? "ok  " : "FAIL",
+         kt, static_cast<unsigned long long>(nseg), n, pairs, seg_passes);
+  fflush(stdout);
+  if (!ok) ++failures;
+}
+
 template <typename K>
 static void run_merge_split(int kt, size_t n, uint64_t p, bool pairs, const char* dist) {
   std::vector<uint64_t> bits;
@@ -177,6 +203,18 @@ int main(int argc, char** argv) {
     run_merge<uint32_t>(MS_KEY_U32, {3000, 0, 2500, 1});
     run_merge<uint32_t>(MS_KEY_I32, {20000, 30000, 5, 70000});
     run_merge_split<uint32_t>(MS_KEY_I32, 5 * 4001, 5, true, "few");
+    // overlapping segments whose tiles exceed the tile table: both paths
+    run_malformed<uint32_t>(MS_KEY_I32, {0, 30000, 10000, 50000, 20000, 60000}, 60000, true, 1);
+    run_malformed<uint32_t>(MS_KEY_U32, {0, 15000, 5000, 12000, 3000, 20000}, 20000, false, 1);
+  }
+  if (what == "malformed") {
+    for (int sp : {1, 0}) {
+      run_malformed<uint32_t>(MS_KEY_I32, {0, 30000, 10000, 50000, 20000, 60000}, 60000, true, sp);
+      run_malformed<uint32_t>(MS_KEY_I32, {0, 30000, 10000, 50000, 20000, 60000}, 60000, false, sp);
+      run_malformed<uint64_t>(MS_KEY_U64, {0, 70000, 20000, 60000}, 60000, true, sp);
+      run_malformed<uint32_t>(MS_KEY_U32, {0, 15000, 5000, 12000, 3000, 20000}, 20000, false, sp);
+      run_malformed<uint32_t>(MS_KEY_U32, {0, 40000, 40000, 100, 100, 50000}, 50000, true, sp);
+    }
   }
   if (what == "all" || what == "sort") {
     for (int threads : {256, 512, 1024}) {
