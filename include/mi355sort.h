@@ -101,8 +101,9 @@ ms_status sort_pairs(const void *keys_in, const uint32_t *vals_in, void *keys_ou
  * than 8,192 keys are sorted by whole-device digit passes over all of them
  * (unless MS_TUNE_SEG_PASSES is 0), other calls by one launch of a persistent
  * kernel whose workgroups each take whole segments; the result is the same.
- * By default calls of 2^32 keys or more take the digit passes whatever the
- * segment lengths.  num_segments = 0 requires
+ * The persistent kernel counts a segment's keys in 32 bits: on that path
+ * every segment must hold fewer than 2^32 keys (a longer one is left in an
+ * unspecified order, with no access outside it).  num_segments = 0 requires
  * n_total = 0.  Errors: MS_EINVAL for NULL pointers with n_total > 0, a NULL
  * offsets array with num_segments > 0, num_segments = 0 with n_total > 0, a
  * short workspace, or only one of vals_in / vals_out given.
@@ -176,12 +177,9 @@ const char *ms_last_error(void);
  *                         sorts use 512.
  *   MS_TUNE_SEG_PASSES    1 (the default): sort_segmented runs whole-device
  *                         digit passes when the segments average more than
- *                         8,192 keys (or the call has 2^32 keys or more);
- *                         0: every sort_segmented call is one launch of the
- *                         persistent kernel, whose workgroups each take whole
- *                         segments, which must then hold fewer than 2^32
- *                         keys each (longer ones are not sorted; accesses
- *                         stay inside their segment).
+ *                         8,192 keys; 0: every sort_segmented call is one
+ *                         launch of the persistent kernel, whose workgroups
+ *                         each take whole segments.
  * ms_tune_set returns MS_EINVAL for an unknown parameter or value;
  * ms_tune_get returns the current value (0 for an unknown parameter).
  */

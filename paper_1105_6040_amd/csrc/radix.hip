@@ -679,13 +679,24 @@ __device__ __forceinline__ uint32_t segment_tiles(const uint64_t* off, uint64_t 
 // Tiles of this block's segments, each thread summing kSegPlanPerThread
 // consecutive segments; returns the thread's exclusive start inside the block
 // and the block total in *total.
+// A segment of this many keys or more needs 64-bit look-back status words
+// (a 30-bit count field holds less); the planner raises *wide for it.
+constexpr uint64_t kWideSegment = 1ull << 30;
+
 __device__ __forceinline__ uint32_t chunk_tiles(const uint64_t* off, uint32_t nseg, uint64_t n, uint32_t tile,
-                                                uint32_t* s_scan, uint32_t* total) {
+                                                uint32_t* wide, uint32_t* s_scan, uint32_t* total) {
   const uint32_t s0 = blockIdx.x * kSegChunk + threadIdx.x * kSegPlanPerThread;
   uint32_t mine = 0;
+  bool long_seg = false;
 #pragma unroll
   for (int i = 0; i < kSegPlanPerThread; ++i)
-    if (s0 + i < nseg) mine += segment_tiles(off, s0 + i, n, tile);
+    if (s0 + i < nseg) {
+      uint64_t b;
+      const uint64_t len = segment_span(off, s0 + i, n, &b);
+      mine += static_cast<uint32_t>((len + tile - 1) / tile);
+      long_seg = long_seg || len >= kWideSegment;
+    }
+  if (long_seg) atomicOr(wide, 1u);
   const uint32_t start = block_exclusive_scan<kSegPlanThreads>(mine, s_scan);
   __syncthreads();
   if (threadIdx.x == kSegPlanThreads - 1) s_scan[0] = start + mine;
@@ -698,10 +709,11 @@ __device__ __forceinline__ uint32_t chunk_tiles(const uint64_t* off, uint32_t ns
 // Plan step 1: tiles per chunk of segments.
 __global__ __launch_bounds__(kSegPlanThreads) void segsweep_count_kernel(const uint64_t* __restrict__ off,
                                                                         uint32_t nseg, uint64_t n, uint32_t tile,
+                                                                        uint32_t* wide,
                                                                         uint32_t* __restrict__ chunk_start) {
   __shared__ uint32_t s_scan[kSegPlanThreads / kWave];
   uint32_t total;
-  chunk_tiles(off, nseg, n, tile, s_scan, &total);
+  chunk_tiles(off, nseg, n, tile, wide, s_scan, &total);
   if (threadIdx.x == 0) chunk_start[blockIdx.x] = total;
 }
 
@@ -766,14 +778,14 @@ __global__ __launch_bounds__(1024) void segsweep_plan_kernel(uint32_t* __restric
 // its segment by a binary search over the chunk's segment starts in LDS).
 // Returns the chunk's tile count; records from max_tiles on are not written.
 __device__ uint32_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, uint64_t n, uint32_t tile,
-                               uint32_t base, uint32_t max_tiles, SegTile* __restrict__ tiles) {
+                               uint32_t base, uint32_t max_tiles, uint32_t* wide, SegTile* __restrict__ tiles) {
   __shared__ uint32_t s_scan[kSegPlanThreads / kWave];
   __shared__ uint32_t s_start[kSegChunk + 1];  // tile start of each segment of the chunk, block-relative
   __shared__ uint64_t s_off[kSegChunk + 1];    // the chunk's offsets, clamped to n
   const uint32_t first_seg = blockIdx.x * kSegChunk;
   const uint32_t nloc = nseg - first_seg < kSegChunk ? nseg - first_seg : kSegChunk;
   uint32_t total;
-  const uint32_t start = chunk_tiles(off, nseg, n, tile, s_scan, &total);
+  const uint32_t start = chunk_tiles(off, nseg, n, tile, wide, s_scan, &total);
   {
     const uint32_t l0 = threadIdx.x * kSegPlanPerThread;
     uint32_t run = start;
@@ -822,9 +834,9 @@ __device__ uint32_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, 
 __global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const uint64_t* __restrict__ off,
                                                                        uint32_t nseg, uint64_t n, uint32_t tile,
                                                                        const uint32_t* __restrict__ chunk_start,
-                                                                       uint32_t max_tiles,
+                                                                       uint32_t max_tiles, uint32_t* wide,
                                                                        SegTile* __restrict__ tiles) {
-  fill_chunk(off, nseg, n, tile, chunk_start[blockIdx.x], max_tiles, tiles);
+  fill_chunk(off, nseg, n, tile, chunk_start[blockIdx.x], max_tiles, wide, tiles);
 }
 
 // The whole plan in one launch when the segments form one chunk (at most
@@ -832,11 +844,11 @@ __global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const ui
 template <typename K, bool VALS>
 __global__ __launch_bounds__(kSegPlanThreads) void segsweep_plan1_kernel(const uint64_t* __restrict__ off,
                                                                         uint32_t nseg, uint64_t n, uint32_t tile,
-                                                                        uint32_t max_tiles,
+                                                                        uint32_t max_tiles, uint32_t* wide,
                                                                         uint32_t* __restrict__ num_tiles,
                                                                         SegTile* __restrict__ tiles, SortPlan* plan,
                                                                         Buffers buf) {
-  const uint32_t total = fill_chunk(off, nseg, n, tile, 0u, max_tiles, tiles);
+  const uint32_t total = fill_chunk(off, nseg, n, tile, 0u, max_tiles, wide, tiles);
   if (threadIdx.x != 0) return;
   *num_tiles = total < max_tiles ? total : max_tiles;
   write_segsweep_plan<K, VALS>(plan, buf);
@@ -926,7 +938,10 @@ template <typename K, bool VALS, typename C, typename S, int THREADS>
 __global__ __launch_bounds__(THREADS) void segsweep_pass_kernel(
     const SortPlan* __restrict__ plan, int pass, const SegTile* __restrict__ tiles,
     const uint32_t* __restrict__ num_tiles_p, C n, K flip, const C* __restrict__ seg_base, uint32_t* tile_counter,
-    S* status_cur, S* status_next) {
+    S* status_cur, S* status_next, const uint32_t* __restrict__ gate, uint32_t want) {
+  // Lists of 2^30 keys and more launch the pass with both status widths; the
+  // planner's flag (a segment of 2^30 keys or more) lets exactly one run.
+  if (gate != nullptr && *gate != want) return;
   constexpr int kThreads = THREADS;
   constexpr int kKpt = PassCfg<THREADS>::kKpt;
   constexpr int kTile = PassCfg<THREADS>::kTile;
@@ -1294,8 +1309,11 @@ SegSweepLayout segsweep_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64
   size_t off = 0;
   L.plan = off;
   off += align_up(sizeof(SortPlan));
-  L.ctrs = off;  // counters and histograms are cleared together; ctrs[0] receives the tile count
-  off += align_up((1 + kMaxPasses) * sizeof(uint32_t));
+  // Counters and histograms are cleared together: ctrs[0] receives the tile
+  // count, ctrs[1 + p] is pass p's tile ticket, ctrs[1 + kMaxPasses] the
+  // planner's flag for a segment of 2^30 keys or more.
+  L.ctrs = off;
+  off += align_up((2 + kMaxPasses) * sizeof(uint32_t));
   L.hist = off;
   off += align_up(nseg * P * kRadix * cb);
   L.ctrs_hist_bytes = off - L.ctrs;
@@ -1320,7 +1338,22 @@ SegSweepLayout segsweep_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64
   return L;
 }
 
+// One digit pass of the segment passes; gate/want as in the kernel.
 template <typename K, bool VALS, typename C, typename S, int THREADS>
+ms_status launch_segsweep_pass(const SortPlan* plan, int p, const SegTile* records, const uint32_t* num_tiles,
+                               uint64_t n, K flip, const C* base, uint32_t* counter, char* status_cur,
+                               char* status_next, const uint32_t* gate, uint32_t want, uint64_t max_tiles,
+                               hipStream_t s) {
+  const uint64_t blocks = std::min<uint64_t>(
+      max_tiles, resident_blocks(reinterpret_cast<const void*>(&segsweep_pass_kernel<K, VALS, C, S, THREADS>),
+                                 THREADS, 256));
+  MS_LAUNCH("segsweep_pass", (segsweep_pass_kernel<K, VALS, C, S, THREADS>), static_cast<uint32_t>(blocks), THREADS,
+            s, plan, p, records, num_tiles, static_cast<C>(n), flip, base, counter,
+            reinterpret_cast<S*>(status_cur), reinterpret_cast<S*>(status_next), gate, want);
+  return MS_OK;
+}
+
+template <typename K, bool VALS, typename C, int THREADS>
 ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
                        uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
   constexpr int P = sizeof(K);
@@ -1331,8 +1364,9 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   C* base = reinterpret_cast<C*>(ws + L.base);
   uint32_t* chunk_start = reinterpret_cast<uint32_t*>(ws + L.chunks);
   SegTile* records = reinterpret_cast<SegTile*>(ws + L.records);
-  S* status[2] = {reinterpret_cast<S*>(ws + L.status0), reinterpret_cast<S*>(ws + L.status1)};
+  char* status[2] = {ws + L.status0, ws + L.status1};
   const uint32_t* num_tiles = ctrs;
+  uint32_t* wide = ctrs + 1 + kMaxPasses;
 
   MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), L.ctrs_hist_bytes / 16,
             reinterpret_cast<uint4*>(ws + L.status0), L.status_bytes / 16);
@@ -1340,28 +1374,37 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   const uint32_t max_tiles = static_cast<uint32_t>(L.tiles);
   if (L.num_chunks == 1) {
     MS_LAUNCH("segsweep_plan", (segsweep_plan1_kernel<K, VALS>), 1, kSegPlanThreads, s, off, nseg, n, kTile,
-              max_tiles, ctrs, records, plan, buf);
+              max_tiles, wide, ctrs, records, plan, buf);
   } else {
-    MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile,
+    MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile, wide,
               chunk_start);
     MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, 1024, s, chunk_start, L.num_chunks, max_tiles,
               ctrs, plan, buf);
     MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile,
-              static_cast<const uint32_t*>(chunk_start), max_tiles, records);
+              static_cast<const uint32_t*>(chunk_start), max_tiles, wide, records);
   }
   const uint64_t hblocks = std::min<uint64_t>(L.tiles, 2 * device_cus(256));
   MS_LAUNCH("segsweep_hist", (segsweep_hist_kernel<K, C>), static_cast<uint32_t>(hblocks), 256, s,
             static_cast<const K*>(kin), flip, static_cast<const SegTile*>(records), num_tiles, hist);
   MS_LAUNCH("segsweep_base", segsweep_base_kernel<C>, nseg * P, 256, s, off, n, P, kTile,
             static_cast<const C*>(hist), base);
-  const uint64_t blocks = std::min<uint64_t>(
-      L.tiles, resident_blocks(reinterpret_cast<const void*>(&segsweep_pass_kernel<K, VALS, C, S, THREADS>),
-                               THREADS, 256));
+  // Segment-local counts fit 30-bit status fields unless a segment has 2^30
+  // keys or more; below 2^30 keys in all no segment can, and only the 32-bit
+  // form is launched.
   for (int p = 0; p < P; ++p) {
-    S* next = p + 1 < P ? status[(p + 1) & 1] : nullptr;
-    MS_LAUNCH("segsweep_pass", (segsweep_pass_kernel<K, VALS, C, S, THREADS>), static_cast<uint32_t>(blocks),
-              THREADS, s, static_cast<const SortPlan*>(plan), p, static_cast<const SegTile*>(records),
-              num_tiles, static_cast<C>(n), flip, static_cast<const C*>(base), ctrs + 1 + p, status[p & 1], next);
+    char* next = p + 1 < P ? status[(p + 1) & 1] : nullptr;
+    const SortPlan* cplan = plan;
+    const SegTile* crec = records;
+    const C* cbase = base;
+    ms_status st = launch_segsweep_pass<K, VALS, C, uint32_t, THREADS>(
+        cplan, p, crec, num_tiles, n, flip, cbase, ctrs + 1 + p, status[p & 1], next, L.big ? wide : nullptr, 0u,
+        L.tiles, s);
+    if (st != MS_OK) return st;
+    if (L.big) {
+      st = launch_segsweep_pass<K, VALS, C, uint64_t, THREADS>(cplan, p, crec, num_tiles, n, flip, cbase,
+                                                               ctrs + 1 + p, status[p & 1], next, wide, 1u, L.tiles, s);
+      if (st != MS_OK) return st;
+    }
   }
   return MS_OK;
 }
@@ -1373,13 +1416,12 @@ ms_status segsweep_dispatch(const void* kin, const uint32_t* vin, void* kout, ui
   // spilling: 32-bit keys without values.
   if constexpr (sizeof(K) == 4 && !VALS) {
     if (tune_get(MS_TUNE_SEG_PASS_THREADS) == 1024) {
-      if (L.big)
-        return run_segsweep<K, VALS, uint64_t, uint64_t, 1024>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
-      return run_segsweep<K, VALS, uint32_t, uint32_t, 1024>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+      if (L.big) return run_segsweep<K, VALS, uint64_t, 1024>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+      return run_segsweep<K, VALS, uint32_t, 1024>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
     }
   }
-  if (L.big) return run_segsweep<K, VALS, uint64_t, uint64_t, 512>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
-  return run_segsweep<K, VALS, uint32_t, uint32_t, 512>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+  if (L.big) return run_segsweep<K, VALS, uint64_t, 512>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+  return run_segsweep<K, VALS, uint32_t, 512>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
 }
 
 }  // namespace
@@ -1414,9 +1456,9 @@ bool segsweep_eligible(uint64_t n, uint64_t nseg) {
   // per (segment, digit position) in one grid dimension.
   if (nseg < 1 || nseg * kMaxPasses >= (1ull << 31)) return false;
   const uint64_t tiles = (n + SegSweepCfg::kTile - 1) / SegSweepCfg::kTile + nseg;
-  // Segments averaging more than a tile, or any call of 2^32 keys or more
-  // (the other path counts a segment's keys in 32 bits).
-  return (n > kSegSweepMinAverage * nseg || n >= (1ull << 32)) && tiles < (1ull << 32);
+  // Segments averaging more than a tile (this also bounds the per-segment
+  // histograms and bases to 8 KiB per 8,192 keys).
+  return n > kSegSweepMinAverage * nseg && tiles < (1ull << 32);
 }
 
 size_t segsweep_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg) {

@@ -504,9 +504,7 @@ ms_status segmented_sort(const void* keys_in, const uint32_t* vals_in, void* key
   if (nseg == 1) return radix_sort(keys_in, vals_in, keys_out, vals_out, n, kt, ws, ws_bytes, s);
   // Long segments (more than 8,192 keys on average): whole-device digit
   // passes over all of them (the host knows only the counts, which decide),
-  // and any call of 2^32 keys or more (this kernel counts a segment's keys
-  // in 32 bits), unless the caller asked for the one-launch persistent
-  // kernel.
+  // unless the caller asked for the one-launch persistent kernel.
   if (tune_get(MS_TUNE_SEG_PASSES) && segsweep_eligible(n, nseg))
     return segsweep_sort(keys_in, vals_in, keys_out, vals_out, offsets, nseg, n, kt, ws, ws_bytes, s);
   const bool vals = vals_in != nullptr;

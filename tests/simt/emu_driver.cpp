@@ -241,6 +241,7 @@ int main(int argc, char** argv) {
     run_segmented<uint32_t>(MS_KEY_I32, {100000}, true, "sorted");
     run_segmented<uint32_t>(MS_KEY_I32, {8192, 1, 0, 30000, 5, 8193, 100, 16385, 7, 40000}, true, "uniform");
     run_segmented<uint64_t>(MS_KEY_U64, {3, 8192, 20000, 8191, 0, 1, 16384, 9000, 2, 30000}, false, "few");
+    run_segmented<uint32_t>(MS_KEY_I32, {9000, 16383, 12000, 10000, 15000, 9500, 16000, 11000}, true, "uniform");
     ms_tune_set(MS_TUNE_SEG_PASS_THREADS, 1024);
     run_segmented<uint32_t>(MS_KEY_U32, {16384, 16383, 16385, 8191, 8193, 40000}, false, "small");
     run_segmented<uint32_t>(MS_KEY_I32, {8192, 1, 0, 30000, 5, 16384, 100, 16385, 7, 40000}, false, "uniform");

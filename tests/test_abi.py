@@ -146,3 +146,14 @@ def test_tune_parameter_checks():
     assert get(N.MS_TUNE_SEG_PASSES) == old
     assert lib.ms_tune_set(6, 1) == N.MS_EINVAL  # MS_TUNE_COUNT is no parameter
     assert get(6) == 0
+
+
+def test_segmented_workspace_stays_near_the_keys():
+    """sort_segmented's workspace is the ping-pong copy of the keys plus a
+    bounded overhead on either path (host arithmetic only): the segment
+    passes only take segments averaging more than 8,192 keys, whose
+    per-segment histograms and bases cost at most 1 B per key."""
+    ws = N.workspace_size
+    for n, nseg in ((4_563_337_368, 50_000), (1 << 32, 1 << 26), (10**6, 3), (10**6, 10**5), (1 << 31, 1 << 18)):
+        b = ws(N.MS_OP_SORT_SEGMENTED, N.MS_KEY_I32, False, n, nseg)
+        assert 4 * n <= b <= 1.3 * 4 * n + 16 * nseg + (1 << 20), (n, nseg, b)

@@ -560,9 +560,27 @@ def test_big_list_sort_pairs_64bit_counters():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("lengths", [[(1 << 30) + 5, 7, 100_000], [70_000, (1 << 30) + 1, 3]])
+def test_big_segment_wide_status(lengths):
+    """A segment of more than 2^30 keys: the planner flags it and the passes
+    run with 64-bit look-back status words (the 32-bit form is launched too
+    and returns at once).  Every segment equals torch's sort of it."""
+    off = inputs.offsets_from_lengths(np.array(lengths))
+    n = int(off[-1])
+    say(f"big segment, wide status n={n}")
+    k = _device_keys(n, 33)
+    out = api.sort_segmented(k, dev(off))
+    for s in range(len(lengths)):
+        a, b = int(off[s]), int(off[s + 1])
+        assert torch.equal(out[a:b], torch.sort(k[a:b]).values), s
+    del out, k
+    torch.cuda.empty_cache()
+
+
 def test_big_segments_64bit_counters():
     """Three segments of 2^30 + 11 keys in all (whole-device segment passes
-    with 64-bit counters): every segment equals torch's sort of it."""
+    with 64-bit bases; every segment below 2^30 keys, so 32-bit look-back
+    status words): every segment equals torch's sort of it."""
     lengths = [(1 << 29) + 7, 3, (1 << 29) + 1]
     off = inputs.offsets_from_lengths(np.array(lengths))
     n = int(off[-1])
