@@ -671,48 +671,47 @@ __device__ __forceinline__ uint64_t segment_span(const uint64_t* off, uint64_t s
   return e > b ? e - b : 0;
 }
 
-__device__ __forceinline__ uint32_t segment_tiles(const uint64_t* off, uint64_t s, uint64_t n, uint32_t tile) {
+__device__ __forceinline__ uint64_t segment_tiles(const uint64_t* off, uint64_t s, uint64_t n, uint32_t tile) {
   uint64_t b;
-  return static_cast<uint32_t>((segment_span(off, s, n, &b) + tile - 1) / tile);
+  return (segment_span(off, s, n, &b) + tile - 1) / tile;
 }
 
-// Tiles of this block's segments, each thread summing kSegPlanPerThread
-// consecutive segments; returns the thread's exclusive start inside the block
-// and the block total in *total.
 // A segment of this many keys or more needs 64-bit look-back status words
 // (a 30-bit count field holds less); the planner raises *wide for it.
 constexpr uint64_t kWideSegment = 1ull << 30;
 
-__device__ __forceinline__ uint32_t chunk_tiles(const uint64_t* off, uint32_t nseg, uint64_t n, uint32_t tile,
-                                                uint32_t* wide, uint32_t* s_scan, uint32_t* total) {
+// Tile counts are summed in 64 bits: offsets that break the contract
+// (overlapping segments) may ask for more tiles than 32 bits count, and a
+// wrapped sum would leave stale records inside the table.
+static_assert(kSegPlanThreads == kRadix, "the planner's block scans cover kRadix threads");
+
+// Tiles of this block's segments, each thread summing kSegPlanPerThread
+// consecutive segments; returns the thread's exclusive start inside the block
+// and the block total in *total.
+__device__ __forceinline__ uint64_t chunk_tiles(const uint64_t* off, uint32_t nseg, uint64_t n, uint32_t tile,
+                                                uint32_t* wide, uint64_t* s_scan, uint64_t* total) {
   const uint32_t s0 = blockIdx.x * kSegChunk + threadIdx.x * kSegPlanPerThread;
-  uint32_t mine = 0;
+  uint64_t mine = 0;
   bool long_seg = false;
 #pragma unroll
   for (int i = 0; i < kSegPlanPerThread; ++i)
     if (s0 + i < nseg) {
       uint64_t b;
       const uint64_t len = segment_span(off, s0 + i, n, &b);
-      mine += static_cast<uint32_t>((len + tile - 1) / tile);
+      mine += (len + tile - 1) / tile;
       long_seg = long_seg || len >= kWideSegment;
     }
   if (long_seg) atomicOr(wide, 1u);
-  const uint32_t start = block_exclusive_scan<kSegPlanThreads>(mine, s_scan);
-  __syncthreads();
-  if (threadIdx.x == kSegPlanThreads - 1) s_scan[0] = start + mine;
-  __syncthreads();
-  *total = s_scan[0];
-  __syncthreads();
-  return start;
+  return block_exclusive_scan_radix<kSegPlanThreads>(mine, s_scan, total);
 }
 
 // Plan step 1: tiles per chunk of segments.
 __global__ __launch_bounds__(kSegPlanThreads) void segsweep_count_kernel(const uint64_t* __restrict__ off,
                                                                         uint32_t nseg, uint64_t n, uint32_t tile,
                                                                         uint32_t* wide,
-                                                                        uint32_t* __restrict__ chunk_start) {
-  __shared__ uint32_t s_scan[kSegPlanThreads / kWave];
-  uint32_t total;
+                                                                        uint64_t* __restrict__ chunk_start) {
+  __shared__ uint64_t s_scan[kRadix / kWave];
+  uint64_t total;
   chunk_tiles(off, nseg, n, tile, wide, s_scan, &total);
   if (threadIdx.x == 0) chunk_start[blockIdx.x] = total;
 }
@@ -747,63 +746,62 @@ __device__ void write_segsweep_plan(SortPlan* plan, const Buffers& buf) {
 // Plan step 2 (one block): chunk starts by an exclusive scan of their tile
 // counts, the tile count, and the pass plan.
 template <typename K, bool VALS>
-__global__ __launch_bounds__(1024) void segsweep_plan_kernel(uint32_t* __restrict__ chunk_start, uint32_t chunks,
-                                                             uint32_t max_tiles, uint32_t* __restrict__ num_tiles,
-                                                             SortPlan* plan, Buffers buf) {
-  __shared__ uint32_t s_scan[1024 / kWave];
-  __shared__ uint32_t s_carry;
+__global__ __launch_bounds__(kSegPlanThreads) void segsweep_plan_kernel(uint64_t* __restrict__ chunk_start,
+                                                                       uint32_t chunks, uint32_t max_tiles,
+                                                                       uint32_t* __restrict__ num_tiles,
+                                                                       SortPlan* plan, Buffers buf) {
+  __shared__ uint64_t s_scan[kRadix / kWave];
   const int tid = threadIdx.x;
-  if (tid == 0) s_carry = 0;
-  __syncthreads();
-  for (uint32_t c0 = 0; c0 < chunks; c0 += 1024) {
+  uint64_t carry = 0;  // the same in every thread
+  for (uint32_t c0 = 0; c0 < chunks; c0 += kSegPlanThreads) {
     const uint32_t c = c0 + tid;
-    const uint32_t v = c < chunks ? chunk_start[c] : 0u;
-    const uint32_t ex = block_exclusive_scan<1024>(v, s_scan);
-    const uint32_t carry = s_carry;
+    const uint64_t v = c < chunks ? chunk_start[c] : 0u;
+    uint64_t sum;
+    const uint64_t ex = block_exclusive_scan_radix<kSegPlanThreads>(v, s_scan, &sum);
     if (c < chunks) chunk_start[c] = carry + ex;
-    __syncthreads();
-    if (tid == 1023) s_carry = carry + ex + v;
-    __syncthreads();
+    carry += sum;
   }
   if (tid != 0) return;
   // Offsets within the contract give at most max_tiles tiles (the size of
   // the record and status tables); overlapping ones may give more, which
   // are dropped.
-  *num_tiles = s_carry < max_tiles ? s_carry : max_tiles;
+  *num_tiles = static_cast<uint32_t>(carry < max_tiles ? carry : max_tiles);
   write_segsweep_plan<K, VALS>(plan, buf);
 }
 
 // Plan step 3: the records of this block's chunk of segments, whose first
 // tile is number `base`; written by all threads of the block (a tile finds
 // its segment by a binary search over the chunk's segment starts in LDS).
-// Returns the chunk's tile count; records from max_tiles on are not written.
-__device__ uint32_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, uint64_t n, uint32_t tile,
-                               uint32_t base, uint32_t max_tiles, uint32_t* wide, SegTile* __restrict__ tiles) {
-  __shared__ uint32_t s_scan[kSegPlanThreads / kWave];
+// Records from max_tiles on are not written: the local starts are held
+// saturated at the room left below max_tiles.  Returns the chunk's tile
+// count.
+__device__ uint64_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, uint64_t n, uint32_t tile,
+                               uint64_t base, uint32_t max_tiles, uint32_t* wide, SegTile* __restrict__ tiles) {
+  __shared__ uint64_t s_scan[kRadix / kWave];
   __shared__ uint32_t s_start[kSegChunk + 1];  // tile start of each segment of the chunk, block-relative
   __shared__ uint64_t s_off[kSegChunk + 1];    // the chunk's offsets, clamped to n
   const uint32_t first_seg = blockIdx.x * kSegChunk;
   const uint32_t nloc = nseg - first_seg < kSegChunk ? nseg - first_seg : kSegChunk;
-  uint32_t total;
-  const uint32_t start = chunk_tiles(off, nseg, n, tile, wide, s_scan, &total);
+  const uint32_t room = static_cast<uint32_t>(base < max_tiles ? max_tiles - base : 0u);
+  uint64_t total;
+  const uint64_t start = chunk_tiles(off, nseg, n, tile, wide, s_scan, &total);
   {
     const uint32_t l0 = threadIdx.x * kSegPlanPerThread;
-    uint32_t run = start;
+    uint64_t run = start;
 #pragma unroll
     for (int i = 0; i < kSegPlanPerThread; ++i)
       if (l0 + i < nloc) {
-        s_start[l0 + i] = run;
+        s_start[l0 + i] = static_cast<uint32_t>(run < room ? run : room);
         run += segment_tiles(off, first_seg + l0 + i, n, tile);
       }
-    if (threadIdx.x == 0) s_start[nloc] = total;
+    if (threadIdx.x == 0) s_start[nloc] = static_cast<uint32_t>(total < room ? total : room);
     for (uint32_t i = threadIdx.x; i <= nloc; i += kSegPlanThreads) {
       const uint64_t v = off[first_seg + i];
       s_off[i] = v < n ? v : n;
     }
   }
   __syncthreads();
-  const uint32_t room = base < max_tiles ? max_tiles - base : 0u;
-  const uint32_t end = total < room ? total : room;
+  const uint32_t end = s_start[nloc];
   for (uint32_t t = threadIdx.x; t < end; t += kSegPlanThreads) {
     // The last local segment whose start is <= t: a non-empty one, since
     // t < its successor's start.
@@ -833,7 +831,7 @@ __device__ uint32_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, 
 
 __global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const uint64_t* __restrict__ off,
                                                                        uint32_t nseg, uint64_t n, uint32_t tile,
-                                                                       const uint32_t* __restrict__ chunk_start,
+                                                                       const uint64_t* __restrict__ chunk_start,
                                                                        uint32_t max_tiles, uint32_t* wide,
                                                                        SegTile* __restrict__ tiles) {
   fill_chunk(off, nseg, n, tile, chunk_start[blockIdx.x], max_tiles, wide, tiles);
@@ -848,9 +846,9 @@ __global__ __launch_bounds__(kSegPlanThreads) void segsweep_plan1_kernel(const u
                                                                         uint32_t* __restrict__ num_tiles,
                                                                         SegTile* __restrict__ tiles, SortPlan* plan,
                                                                         Buffers buf) {
-  const uint32_t total = fill_chunk(off, nseg, n, tile, 0u, max_tiles, wide, tiles);
+  const uint64_t total = fill_chunk(off, nseg, n, tile, 0u, max_tiles, wide, tiles);
   if (threadIdx.x != 0) return;
-  *num_tiles = total < max_tiles ? total : max_tiles;
+  *num_tiles = static_cast<uint32_t>(total < max_tiles ? total : max_tiles);
   write_segsweep_plan<K, VALS>(plan, buf);
 }
 
@@ -1320,7 +1318,7 @@ SegSweepLayout segsweep_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64
   L.base = off;
   off += align_up(nseg * P * kRadix * cb);
   L.chunks = off;
-  off += align_up(static_cast<size_t>(L.num_chunks) * sizeof(uint32_t));
+  off += align_up(static_cast<size_t>(L.num_chunks) * sizeof(uint64_t));
   L.records = off;
   off += align_up(static_cast<size_t>(L.tiles) * sizeof(SegTile));
   L.status_bytes = align_up(static_cast<size_t>(L.tiles) * kRadix * cb);
@@ -1362,7 +1360,7 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   uint32_t* ctrs = reinterpret_cast<uint32_t*>(ws + L.ctrs);
   C* hist = reinterpret_cast<C*>(ws + L.hist);
   C* base = reinterpret_cast<C*>(ws + L.base);
-  uint32_t* chunk_start = reinterpret_cast<uint32_t*>(ws + L.chunks);
+  uint64_t* chunk_start = reinterpret_cast<uint64_t*>(ws + L.chunks);
   SegTile* records = reinterpret_cast<SegTile*>(ws + L.records);
   char* status[2] = {ws + L.status0, ws + L.status1};
   const uint32_t* num_tiles = ctrs;
@@ -1378,10 +1376,10 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   } else {
     MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile, wide,
               chunk_start);
-    MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, 1024, s, chunk_start, L.num_chunks, max_tiles,
-              ctrs, plan, buf);
+    MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, kSegPlanThreads, s, chunk_start, L.num_chunks,
+              max_tiles, ctrs, plan, buf);
     MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile,
-              static_cast<const uint32_t*>(chunk_start), max_tiles, wide, records);
+              static_cast<const uint64_t*>(chunk_start), max_tiles, wide, records);
   }
   const uint64_t hblocks = std::min<uint64_t>(L.tiles, 2 * device_cus(256));
   MS_LAUNCH("segsweep_hist", (segsweep_hist_kernel<K, C>), static_cast<uint32_t>(hblocks), 256, s,

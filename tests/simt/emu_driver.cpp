@@ -207,6 +207,16 @@ int main(int argc, char** argv) {
     run_malformed<uint32_t>(MS_KEY_I32, {0, 30000, 10000, 50000, 20000, 60000}, 60000, true, 1);
     run_malformed<uint32_t>(MS_KEY_U32, {0, 15000, 5000, 12000, 3000, 20000}, 20000, false, 1);
   }
+  if (what == "manyseg") {  // hundreds of short segments (with lowered thresholds: several planning chunks)
+    std::vector<uint64_t> lens;
+    for (int i = 0; i < 700; ++i) lens.push_back(rnd() % 300);
+    lens[5] = 0;
+    lens[699] = 0;
+    run_segmented<uint32_t>(MS_KEY_I32, lens, true, "uniform");
+    lens.resize(300);
+    run_segmented<uint64_t>(MS_KEY_U64, lens, false, "few");
+    run_malformed<uint32_t>(MS_KEY_U32, {0, 9000, 0, 9000, 0, 9000, 0, 9000, 3000, 9000}, 9000, false, 1);
+  }
   if (what == "malformed") {
     for (int sp : {1, 0}) {
       run_malformed<uint32_t>(MS_KEY_I32, {0, 30000, 10000, 50000, 20000, 60000}, 60000, true, sp);
