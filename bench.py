@@ -141,6 +141,9 @@ def main():
                     help="instead of the headline: the process-count sweep (paper's method, p = 1..64)")
     ap.add_argument("--memory", action="store_true",
                     help="instead of the headline: device bytes against list size (no GPU needed)")
+    ap.add_argument("--segments", action="store_true",
+                    help="instead of the headline: the 50,000-segment batched sort alone, after a 1 GiB "
+                         "device copy (the copy calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (no multi-GPU path is built)",
@@ -161,6 +164,15 @@ def main():
     stream = torch.cuda.current_stream(dev)
     if args.psweep:
         print(json.dumps(process_sweep(dev, stream)), flush=True)
+        return
+    if args.segments:
+        a = torch.zeros(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        _, cper = time_steps(lambda: b.copy_(a), 5, 2, stream)
+        del a, b
+        res = segments_workload(dev, stream)
+        res["copy_probe_GBps"] = round(2 * (1 << 28) * 4 / (sorted(cper)[len(cper) // 2] * 1e-3) / 1e9, 1)
+        print(json.dumps({"segments_50k": res}), flush=True)
         return
     n = 1 << 28
     log("generating 2^28 int32 uniform keys")
