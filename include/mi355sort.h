@@ -85,22 +85,39 @@ ms_status sort_keys(const void *keys_in, void *keys_out, uint64_t n, ms_key_type
                     size_t ws_bytes, void *stream);
 
 /*
- * Sort n (key, value) pairs by key, stably: a value moves with its key and
- * equal keys keep their input order.  In-place is allowed when keys_out ==
- * keys_in AND vals_out == vals_in.  Errors as for sort_keys.
+ * Sort n (key, value) pairs by key, stably (Figure 1 with p = 1, the items
+ * carrying a payload): the list of Section 3.2 is put in ascending key order,
+ * a value moves with its key and equal keys keep their input order (the
+ * order a left-first merge in Figure 3's merge sort keeps).  In-place is
+ * allowed when keys_out == keys_in AND vals_out == vals_in.  Errors as for
+ * sort_keys, plus MS_EINVAL when only one of keys and values is in place.
  */
 ms_status sort_pairs(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
                      uint64_t n, ms_key_type kt, void *ws, size_t ws_bytes, void *stream);
 
 /*
- * The scatter and sorting phases of Figure 1 for many lists at once: each
+ * The scatter phase of Figure 1 (the master computes s = n/p and hands out
+ * contiguous sub-lists): writes the p + 1 boundaries of p contiguous parts of
+ * a list of n items to offsets_out, a device array of num_parts + 1 uint64_t
+ * owned by the caller: part i = [floor(i*n/p), floor((i+1)*n/p)), exactly
+ * (the product i*n is formed in 128 bits), so parts differ in size by at most
+ * one when p does not divide n and are s = n/p each when it does.  The
+ * result is the offsets argument of sort_segmented and merge_runs for the
+ * paper's method.  One small launch on `stream`; no key moves.  Errors:
+ * MS_EINVAL for num_parts = 0 or UINT64_MAX, or a NULL offsets_out.
+ */
+ms_status part_offsets(uint64_t n, uint64_t num_parts, uint64_t *offsets_out, void *stream);
+
+/*
+ * The sorting phase of Figure 1 for many lists at once: each
  * segment [seg_offsets[s], seg_offsets[s+1]) of the input is sorted on its
  * own (no item crosses a segment boundary; empty segments are allowed).
  * vals_in / vals_out may both be NULL for a key-only sort.  In-place is
  * allowed under the same rule as sort_pairs.  Several segments averaging more
  * than 8,192 keys are sorted by whole-device digit passes over all of them
- * (unless MS_TUNE_SEG_PASSES is 0), other calls by one launch of a persistent
- * kernel whose workgroups each take whole segments; the result is the same.
+ * (unless MS_TUNE_SEG_PASSES is 0), other calls by three small planning
+ * launches and one launch of a persistent kernel whose workgroups each take
+ * whole segments; the result is the same.
  * The persistent kernel counts a segment's keys in 32 bits: on that path
  * every segment must hold fewer than 2^32 keys (a longer one is left in an
  * unspecified order, with no access outside it).  num_segments = 0 requires

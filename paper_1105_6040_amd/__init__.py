@@ -4,7 +4,7 @@ The compute path is the HIP library ``libmi355sort.so`` behind the C ABI of
 ``include/mi355sort.h``; ``api`` wraps it for PyTorch tensors.  Importing this
 package does not load the library or PyTorch; the sort calls do.
 """
-_API = ("sort_keys", "sort_pairs", "sort_segmented", "merge_runs", "sort_parts", "key_type")
+_API = ("sort_keys", "sort_pairs", "part_offsets", "sort_segmented", "merge_runs", "merge_split", "key_type")
 
 
 def __getattr__(name):

@@ -45,6 +45,19 @@ def _check_vals(vals: torch.Tensor, n: int, what: str = "values") -> None:
         raise ValueError(f"{what} must have as many entries as the keys")
 
 
+def _check_out(out: torch.Tensor, like: torch.Tensor, what: str) -> None:
+    """A caller's output tensor must be a contiguous 1-D GPU tensor on the
+    input's device, of the input's dtype and length: the library writes
+    exactly n elements of that size through its pointer."""
+    _check_1d(out, what)
+    if out.device != like.device:
+        raise ValueError(f"{what} must be on {like.device} (got {out.device})")
+    if out.dtype != like.dtype:
+        raise TypeError(f"{what} must have dtype {like.dtype} (got {out.dtype})")
+    if out.numel() != like.numel():
+        raise ValueError(f"{what} must have {like.numel()} entries (got {out.numel()})")
+
+
 def _check_offsets(off: torch.Tensor, what: str) -> None:
     _check_1d(off, what)
     if off.dtype not in (torch.uint64, torch.int64):
@@ -65,6 +78,8 @@ def workspace(op: int, kt: int, has_values: bool, n: int, num_segments: int, dev
               provided: Optional[torch.Tensor] = None) -> Tuple[Optional[torch.Tensor], int]:
     need = N.workspace_size(op, kt, has_values, n, num_segments)
     if provided is not None:
+        if not provided.is_cuda or provided.device != torch.device(device) or not provided.is_contiguous():
+            raise ValueError(f"workspace must be a contiguous tensor on {device}")
         if provided.numel() * provided.element_size() < need:
             raise ValueError(f"workspace too small: need {need} bytes")
         return provided, provided.numel() * provided.element_size()
@@ -80,9 +95,7 @@ def sort_keys(keys: torch.Tensor, out: Optional[torch.Tensor] = None,
     kt = key_type(keys)
     n = keys.numel()
     out = torch.empty_like(keys) if out is None else out
-    _check_1d(out, "out")
-    if out.dtype != keys.dtype or out.numel() != n:
-        raise ValueError("out must match keys in dtype and length")
+    _check_out(out, keys, "out")
     w, wb = workspace(N.MS_OP_SORT_KEYS, kt, False, n, 0, keys.device, ws)
     N.check(N.lib().sort_keys(_ptr(keys), _ptr(out), n, kt, _ptr(w), wb, _stream(keys.device)), "sort_keys")
     return out
@@ -96,10 +109,12 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, keys_out: Optional[torch.
     kt = key_type(keys)
     n = keys.numel()
     _check_vals(vals, n)
+    if vals.device != keys.device:
+        raise ValueError(f"values must be on {keys.device} (got {vals.device})")
     keys_out = torch.empty_like(keys) if keys_out is None else keys_out
     vals_out = torch.empty_like(vals) if vals_out is None else vals_out
-    _check_1d(keys_out, "keys_out")
-    _check_vals(vals_out, n, "vals_out")
+    _check_out(keys_out, keys, "keys_out")
+    _check_out(vals_out, vals, "vals_out")
     w, wb = workspace(N.MS_OP_SORT_PAIRS, kt, True, n, 0, keys.device, ws)
     N.check(N.lib().sort_pairs(_ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), n, kt, _ptr(w), wb,
                                _stream(keys.device)), "sort_pairs")
@@ -107,17 +122,35 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, keys_out: Optional[torch.
 
 
 def part_offsets(n: int, p: int, device=None) -> torch.Tensor:
-    """Scatter phase (Figure 1): split a list of n items into p contiguous
-    parts of about n/p items; part i = [floor(i*n/p), floor((i+1)*n/p)), so
-    part sizes differ by at most one when p does not divide n.  Returns the
-    p + 1 boundaries as a uint64 tensor (on `device` if given), ready for
+    """Scatter phase (Figure 1): the p + 1 boundaries of p contiguous parts of
+    a list of n items, part i = [floor(i*n/p), floor((i+1)*n/p)), computed by
+    the library's ``part_offsets`` entry point on the GPU (`device`, default
+    the current one).  Returns a uint64 device tensor, ready for
     sort_segmented and merge_runs.  No data moves."""
     if p < 1:
         raise ValueError(f"part_offsets: p must be at least 1 (got {p})")
     if n < 0:
         raise ValueError(f"part_offsets: n must be non-negative (got {n})")
-    off = torch.tensor([(i * n) // p for i in range(p + 1)], dtype=torch.uint64)
-    return off if device is None else off.to(device)
+    if n >= 1 << 64 or p >= (1 << 64) - 1:
+        raise ValueError("part_offsets: n and p must fit in 64 bits")
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    if dev.type != "cuda":
+        raise ValueError(f"part_offsets: the library computes the offsets on a GPU, not on {dev}")
+    off = torch.empty(p + 1, dtype=torch.uint64, device=dev)
+    N.check(N.lib().part_offsets(n, p, _ptr(off), _stream(dev)), "part_offsets")
+    return off
+
+
+def _outputs(keys, vals, keys_out, vals_out):
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    _check_out(keys_out, keys, "keys_out")
+    if vals is None:
+        if vals_out is not None:
+            raise ValueError("vals_out given without vals")
+        return keys_out, None
+    vals_out = torch.empty_like(vals) if vals_out is None else vals_out
+    _check_out(vals_out, vals, "vals_out")
+    return keys_out, vals_out
 
 
 def sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, vals: Optional[torch.Tensor] = None,
@@ -126,14 +159,16 @@ def sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, vals: Optional[tor
     """Sort every segment [offsets[s], offsets[s+1]) on its own.  Returns keys or (keys, vals)."""
     _check_1d(keys, "keys")
     _check_offsets(offsets, "offsets")
+    if offsets.device != keys.device:
+        raise ValueError(f"offsets must be on {keys.device} (got {offsets.device})")
     kt = key_type(keys)
     n = keys.numel()
     nseg = offsets.numel() - 1
     if vals is not None:
         _check_vals(vals, n)
-    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
-    if vals is not None and vals_out is None:
-        vals_out = torch.empty_like(vals)
+        if vals.device != keys.device:
+            raise ValueError(f"values must be on {keys.device} (got {vals.device})")
+    keys_out, vals_out = _outputs(keys, vals, keys_out, vals_out)
     w, wb = workspace(N.MS_OP_SORT_SEGMENTED, kt, vals is not None, n, nseg, keys.device, ws)
     N.check(N.lib().sort_segmented(_ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), _ptr(offsets), nseg,
                                    n, kt, _ptr(w), wb, _stream(keys.device)), "sort_segmented")
@@ -146,14 +181,16 @@ def merge_runs(keys: torch.Tensor, offsets: torch.Tensor, vals: Optional[torch.T
     """Stable merge of the sorted runs [offsets[r], offsets[r+1]).  Returns keys or (keys, vals)."""
     _check_1d(keys, "keys")
     _check_offsets(offsets, "offsets")
+    if offsets.device != keys.device:
+        raise ValueError(f"offsets must be on {keys.device} (got {offsets.device})")
     kt = key_type(keys)
     n = keys.numel()
     nruns = offsets.numel() - 1
     if vals is not None:
         _check_vals(vals, n)
-    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
-    if vals is not None and vals_out is None:
-        vals_out = torch.empty_like(vals)
+        if vals.device != keys.device:
+            raise ValueError(f"values must be on {keys.device} (got {vals.device})")
+    keys_out, vals_out = _outputs(keys, vals, keys_out, vals_out)
     w, wb = workspace(N.MS_OP_MERGE_RUNS, kt, vals is not None, n, nruns, keys.device, ws)
     N.check(N.lib().merge_runs(_ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), _ptr(offsets), nruns, n,
                                kt, _ptr(w), wb, _stream(keys.device)), "merge_runs")
@@ -170,9 +207,9 @@ def merge_split(keys: torch.Tensor, p: int, vals: Optional[torch.Tensor] = None,
     n = keys.numel()
     if vals is not None:
         _check_vals(vals, n)
-    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
-    if vals is not None and vals_out is None:
-        vals_out = torch.empty_like(vals)
+        if vals.device != keys.device:
+            raise ValueError(f"values must be on {keys.device} (got {vals.device})")
+    keys_out, vals_out = _outputs(keys, vals, keys_out, vals_out)
     w, wb = workspace(N.MS_OP_MERGE_SPLIT, kt, vals is not None, n, p, keys.device, ws)
     N.check(N.lib().merge_split(_ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), n, p, kt, _ptr(w), wb,
                                 _stream(keys.device)), "merge_split")

@@ -127,6 +127,14 @@ ms_status sort_pairs(const void* keys_in, const uint32_t* vals_in, void* keys_ou
                         static_cast<hipStream_t>(stream));
 }
 
+ms_status part_offsets(uint64_t n, uint64_t num_parts, uint64_t* offsets_out, void* stream) {
+  if (num_parts == 0) return fail(MS_EINVAL, "part_offsets: num_parts must be at least 1");
+  if (num_parts == UINT64_MAX)
+    return fail(MS_EINVAL, "part_offsets: num_parts + 1 boundaries do not fit in 64 bits");
+  if (!offsets_out) return fail(MS_EINVAL, "part_offsets: NULL offsets_out");
+  return ms::partition_offsets(n, num_parts, offsets_out, static_cast<hipStream_t>(stream));
+}
+
 static ms_status check_ranged(const char* what, const void* keys_in, const uint32_t* vals_in, const void* keys_out,
                               const uint32_t* vals_out, const uint64_t* offsets, uint64_t count,
                               uint64_t n_total, ms_key_type kt) {

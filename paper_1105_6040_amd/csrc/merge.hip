@@ -338,9 +338,21 @@ ms_status run_merge(const void* kin, const uint32_t* vin, void* kout, uint32_t* 
 // part 0 is copied).  Merging a pair into the same positions and keeping the
 // first s outputs in the lower part is the count-preserving split.
 
+// The scatter phase of Figure 1: the p + 1 boundaries of p contiguous parts,
+// part i = [floor(i*n/p), floor((i+1)*n/p)), so that part sizes differ by at
+// most one when p does not divide n.  i*n is formed in 128 bits: it exceeds
+// 64 bits for lists and part counts both beyond 2^32.
 __global__ __launch_bounds__(256) void part_offsets_kernel(uint64_t* off, uint64_t n, uint64_t p) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 256;
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x; i <= p; i += stride) off[i] = i * (n / p);
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x; i <= p; i += stride)
+    off[i] = static_cast<uint64_t>((static_cast<unsigned __int128>(i) * n) / p);
+}
+
+// Grid of the partition launch: one thread per boundary, at most 65,536
+// workgroups striding over the rest.
+uint32_t part_offsets_blocks(uint64_t p) {
+  const uint64_t b = (p + 256) / 256;
+  return static_cast<uint32_t>(b < 65536 ? b : 65536);
 }
 
 struct SplitLayout {
@@ -376,7 +388,7 @@ ms_status run_merge_split(const void* kin, const uint32_t* vin, void* kout, uint
   uint64_t* off = reinterpret_cast<uint64_t*>(ws + L.off);
   K* alt_k = reinterpret_cast<K*>(ws + L.alt_k);
   uint32_t* alt_v = VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr;
-  MS_LAUNCH("part_offsets", part_offsets_kernel, static_cast<uint32_t>((p + 256) / 256), 256, s, off, n, p);
+  MS_LAUNCH("part_offsets", part_offsets_kernel, part_offsets_blocks(p), 256, s, off, n, p);
   const uint64_t sz = n / p;
   const bool big = n >= kBigTileMin;
   const uint64_t tile = big ? MergeCfg<K, true>::kTile : MergeCfg<K, false>::kTile;
@@ -411,6 +423,11 @@ ms_status run_merge_split(const void* kin, const uint32_t* vin, void* kout, uint
 }
 
 }  // namespace
+
+ms_status partition_offsets(uint64_t n, uint64_t p, uint64_t* off, hipStream_t s) {
+  MS_LAUNCH("part_offsets", part_offsets_kernel, part_offsets_blocks(p), 256, s, off, n, p);
+  return MS_OK;
+}
 
 size_t merge_split_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nparts) {
   return split_layout(kt, has_vals, n, nparts).total;

@@ -59,6 +59,9 @@ ms_status segsweep_sort(const void* keys_in, const uint32_t* vals_in, void* keys
                         const uint64_t* offsets, uint64_t nseg, uint64_t n, ms_key_type kt, void* ws,
                         size_t ws_bytes, hipStream_t s);
 
+// ---- scatter phase: part boundaries ------------------------------------------
+ms_status partition_offsets(uint64_t n, uint64_t p, uint64_t* off, hipStream_t s);
+
 // ---- merge of sorted runs ---------------------------------------------------
 size_t merge_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nruns);
 size_t merge_split_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nparts);

@@ -3,12 +3,14 @@
 // The scatter and sorting phases of the paper's method (Section 3.2,
 // Figure 1 steps 3-9) for many lists at once: every segment of the input is
 // sorted on its own, stably, and nothing crosses a segment boundary.  The
-// host never reads the segment offsets, so one call is two launches whatever
-// the number and sizes of the segments:
+// host never reads the segment offsets, so one call is the same four
+// launches whatever the number and sizes of the segments: three small
+// planning launches whose cost does not grow with the keys, then one
+// persistent sort launch that does all the sorting:
 //
-//   1. plan (one workgroup): segment lengths -> size classes (floor log2) ->
-//      a work list of the non-empty segments, largest class first, so the
-//      longest segments start first (longest-processing-time order);
+//   1. plan (count, base, fill): segment lengths -> size classes (floor
+//      log2) -> a work list of the non-empty segments, largest class first,
+//      so the longest segments start first (longest-processing-time order);
 //   2. sort (persistent workgroups): each workgroup takes the next segment
 //      of the work list from an atomic counter.  Segments of fewer than 1,024
 //      keys are taken eight at a time, one per wave, and each wave sorts its
