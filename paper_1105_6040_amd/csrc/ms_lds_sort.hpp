@@ -18,43 +18,36 @@ struct LdsCfg {
   static constexpr int kTile = kThreads * kKpt;
 };
 
-// In-LDS sort of one short list per workgroup (every pass on-chip).
-//   seg_off == nullptr: a single list [0, n_total).
-//   otherwise:          segment seg = (seg_list ? seg_list[b] : b) of the
-//                       offsets array, clamped to n_total; segments longer
-//                       than one tile are left to other kernels.
-// Internal linkage: every translation unit that launches it owns its instance.
-namespace {
+// LDS of one in-LDS list sort: per-wave digit counters, the key and value
+// stages, scan scratch and the changed-bits words.
 template <typename K, bool VALS>
-__global__ __launch_bounds__(LdsCfg<K>::kThreads) void lds_sort_kernel(
-    const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* kout, uint32_t* vout,
-    const uint64_t* __restrict__ seg_off, const uint32_t* __restrict__ seg_list, uint64_t n_total, K flip) {
+struct LdsSortSmem {
+  static constexpr int kWaves = LdsCfg<K>::kThreads / kWave;
+  uint32_t (*whist)[kRadix];  // kWaves rows
+  K* keys;                    // LdsCfg<K>::kTile entries
+  uint32_t* vals;             // LdsCfg<K>::kTile entries when VALS
+  uint32_t* scan;             // kRadix / kWave entries
+  uint32_t* diff;             // 2 entries
+};
+
+// One workgroup of LdsCfg<K>::kThreads threads sorts the list
+// [begin, begin + len) of kin/vin (1 <= len <= LdsCfg<K>::kTile) into the
+// same positions of kout/vout, every digit pass on-chip.  Contains barriers;
+// every thread of the block calls it.
+template <typename K, bool VALS>
+__device__ __forceinline__ void lds_sort_list(const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* kout,
+                                              uint32_t* vout, uint64_t begin, int len, K flip,
+                                              const LdsSortSmem<K, VALS>& sm) {
   constexpr int kThreads = LdsCfg<K>::kThreads;
   constexpr int kKpt = LdsCfg<K>::kKpt;
-  constexpr int kTile = LdsCfg<K>::kTile;
   constexpr int kWaves = kThreads / kWave;
-  __shared__ uint32_t s_whist[kWaves][kRadix];
-  __shared__ K s_keys[kTile];
-  __shared__ uint32_t s_vals[VALS ? kTile : 1];
-  __shared__ uint32_t s_scan[kRadix / kWave];
-  __shared__ uint32_t s_diff[2];
-
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
   const uint32_t lane = lane_id();
-
-  uint64_t begin = 0, end = n_total;
-  if (seg_off) {
-    const uint64_t s = seg_list ? seg_list[blockIdx.x] : blockIdx.x;
-    begin = seg_off[s];
-    end = seg_off[s + 1];
-    begin = begin < n_total ? begin : n_total;
-    end = end < n_total ? end : n_total;
-    if (end < begin) end = begin;
-  }
-  const uint64_t len64 = end - begin;
-  if (len64 == 0 || len64 > static_cast<uint64_t>(kTile)) return;
-  const int len = static_cast<int>(len64);
+  uint32_t (*s_whist)[kRadix] = sm.whist;
+  K* s_keys = sm.keys;
+  uint32_t* s_vals = sm.vals;
+  uint32_t* s_diff = sm.diff;
 
   const int first = wave * kWave * kKpt + static_cast<int>(lane);
   K keys[kKpt];
@@ -91,7 +84,7 @@ __global__ __launch_bounds__(LdsCfg<K>::kThreads) void lds_sort_kernel(
     wave_rank(keys, shift, rank, wh);
     __syncthreads();
     uint32_t cnt;
-    tile_digit_starts<kThreads>(s_whist, s_scan, &cnt);
+    tile_digit_starts<kThreads>(s_whist, sm.scan, &cnt);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kKpt; ++j) {
@@ -116,6 +109,40 @@ __global__ __launch_bounds__(LdsCfg<K>::kThreads) void lds_sort_kernel(
       if constexpr (VALS) vout[begin + idx] = vals[j];
     }
   }
+}
+
+// In-LDS sort of one short list per workgroup (every pass on-chip).
+//   seg_off == nullptr: a single list [0, n_total).
+//   otherwise:          segment seg = (seg_list ? seg_list[b] : b) of the
+//                       offsets array, clamped to n_total; segments longer
+//                       than one tile are left to other kernels.
+// Internal linkage: every translation unit that launches it owns its instance.
+namespace {
+template <typename K, bool VALS>
+__global__ __launch_bounds__(LdsCfg<K>::kThreads) void lds_sort_kernel(
+    const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* kout, uint32_t* vout,
+    const uint64_t* __restrict__ seg_off, const uint32_t* __restrict__ seg_list, uint64_t n_total, K flip) {
+  constexpr int kTile = LdsCfg<K>::kTile;
+  constexpr int kWaves = LdsCfg<K>::kThreads / kWave;
+  __shared__ uint32_t s_whist[kWaves][kRadix];
+  __shared__ K s_keys[kTile];
+  __shared__ uint32_t s_vals[VALS ? kTile : 1];
+  __shared__ uint32_t s_scan[kRadix / kWave];
+  __shared__ uint32_t s_diff[2];
+
+  uint64_t begin = 0, end = n_total;
+  if (seg_off) {
+    const uint64_t s = seg_list ? seg_list[blockIdx.x] : blockIdx.x;
+    begin = seg_off[s];
+    end = seg_off[s + 1];
+    begin = begin < n_total ? begin : n_total;
+    end = end < n_total ? end : n_total;
+    if (end < begin) end = begin;
+  }
+  const uint64_t len64 = end - begin;
+  if (len64 == 0 || len64 > static_cast<uint64_t>(kTile)) return;
+  const LdsSortSmem<K, VALS> sm = {s_whist, s_keys, s_vals, s_scan, s_diff};
+  lds_sort_list<K, VALS>(kin, vin, kout, vout, begin, static_cast<int>(len64), flip, sm);
 }
 
 }  // namespace

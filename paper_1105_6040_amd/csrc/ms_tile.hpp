@@ -152,6 +152,58 @@ __device__ __forceinline__ void tile_sort_digit(K (&keys)[KPT], uint32_t (&vals)
   tile_split_stage<THREADS, KPT, VALS>(keys, vals, shift + kSubBits, stage_k, stage_v, counts, scan, reload);
 }
 
+// Blocked load of the tile starting at `base` (raw bits: the codec is applied
+// by the caller once the loads have landed); past the end keys read as `pad`
+// and values as 0.
+template <typename K, bool VALS, typename C, int KPT>
+__device__ __forceinline__ void load_tile_keys(gptr<const K> src, gptr<const uint32_t> src_v, C my_base, C n, K pad,
+                                               K (&keys)[KPT], uint32_t (&vals)[KPT]) {
+  const bool vec_ok = (reinterpret_cast<uintptr_t>(src + my_base) % 16 == 0) && my_base + KPT <= n;
+  if (vec_ok) {
+    constexpr int kPer = 16 / sizeof(K);
+    gptr<const uint4> p4 = (gptr<const uint4>)(src + my_base);
+#pragma unroll
+    for (int q = 0; q < KPT / kPer; ++q) {
+      const uint4 v = p4[q];
+      if constexpr (sizeof(K) == 4) {
+        keys[4 * q + 0] = v.x;
+        keys[4 * q + 1] = v.y;
+        keys[4 * q + 2] = v.z;
+        keys[4 * q + 3] = v.w;
+      } else {
+        keys[2 * q + 0] = (static_cast<uint64_t>(v.y) << 32) | v.x;
+        keys[2 * q + 1] = (static_cast<uint64_t>(v.w) << 32) | v.z;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      const C idx = my_base + j;
+      keys[j] = idx < n ? src[idx] : pad;
+    }
+  }
+  if constexpr (VALS) {
+    const bool vvec = (reinterpret_cast<uintptr_t>(src_v + my_base) % 16 == 0) && my_base + KPT <= n;
+    if (vvec) {
+      gptr<const uint4> p4 = (gptr<const uint4>)(src_v + my_base);
+#pragma unroll
+      for (int q = 0; q < KPT / 4; ++q) {
+        const uint4 v = p4[q];
+        vals[4 * q + 0] = v.x;
+        vals[4 * q + 1] = v.y;
+        vals[4 * q + 2] = v.z;
+        vals[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        const C idx = my_base + j;
+        vals[j] = idx < n ? src_v[idx] : 0u;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The same reorder for one wave on its own (64 lanes x KPT keys): used to sort
 // many short lists at once, one per wave.  Lanes exchange data through the
