@@ -164,6 +164,22 @@ ms_status merge_split(const void *keys_in, const uint32_t *vals_in, void *keys_o
                       uint64_t n_total, uint64_t num_parts, ms_key_type kt, void *ws, size_t ws_bytes,
                       void *stream);
 
+/*
+ * sort_keys for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops that must not allocate, harnesses that forbid
+ * hipMalloc.  Same result and same kernels as sort_keys, but the workspace is
+ * a fixed 64 MiB array in the library's own device memory (one per GPU,
+ * held until the process ends) instead of a caller's buffer; nothing is
+ * allocated by the call.  Size limit: n whose sort_keys workspace fits in
+ * 64 MiB, i.e. at most 14,910,784 keys for MS_KEY_I32 / MS_KEY_U32 and
+ * 7,892,992 for MS_KEY_U64; beyond that MS_EINVAL with a message.  Every
+ * call on one GPU shares that GPU's array: calls that overlap in time on
+ * the same GPU (other streams, other host threads) race and give undefined
+ * results; calls ordered on one stream are fine.  keys_out may equal
+ * keys_in.  Errors otherwise as for sort_keys.
+ */
+ms_status sort_keys_noalloc(const void *keys_in, void *keys_out, uint64_t n, ms_key_type kt, void *stream);
+
 /* Text describing the last non-OK status returned on this host thread
  * ("" if none).  The pointer stays valid until the thread's next call. */
 const char *ms_last_error(void);

@@ -23,7 +23,7 @@ MS_KEY_I32, MS_KEY_U32, MS_KEY_U64 = 0, 1, 2
 MS_OP_SORT_KEYS, MS_OP_SORT_PAIRS, MS_OP_SORT_SEGMENTED, MS_OP_MERGE_RUNS, MS_OP_MERGE_SPLIT = 0, 1, 2, 3, 4
 
 EXPORTS = ("ms_workspace_size", "sort_keys", "sort_pairs", "part_offsets", "sort_segmented", "merge_runs",
-           "merge_split", "ms_last_error",
+           "merge_split", "sort_keys_noalloc", "ms_last_error",
            "ms_timing_enable", "ms_timing_reset", "ms_timing_read", "ms_tune_set", "ms_tune_get")
 # ms_tune_param
 MS_TUNE_PASS_THREADS = 0
@@ -67,11 +67,12 @@ def lib() -> ctypes.CDLL:
         L.sort_keys.argtypes = [vp, vp, u64, i32, vp, sz, vp]
         L.sort_pairs.argtypes = [vp, vp, vp, vp, u64, i32, vp, sz, vp]
         L.part_offsets.argtypes = [u64, u64, vp, vp]
+        L.sort_keys_noalloc.argtypes = [vp, vp, u64, i32, vp]
         L.sort_segmented.argtypes = [vp, vp, vp, vp, vp, u64, u64, i32, vp, sz, vp]
         L.merge_runs.argtypes = [vp, vp, vp, vp, vp, u64, u64, i32, vp, sz, vp]
         L.merge_split.argtypes = [vp, vp, vp, vp, u64, u64, i32, vp, sz, vp]
         for fn in ("ms_workspace_size", "sort_keys", "sort_pairs", "part_offsets", "sort_segmented", "merge_runs",
-                   "merge_split", "ms_timing_enable", "ms_timing_reset"):
+                   "merge_split", "sort_keys_noalloc", "ms_timing_enable", "ms_timing_reset"):
             getattr(L, fn).restype = i32
         L.ms_last_error.argtypes = []
         L.ms_last_error.restype = ctypes.c_char_p

@@ -27,6 +27,10 @@
 #define __launch_bounds__(...)
 // Each running block owns an OS thread, so thread-local statics are its LDS.
 #define __shared__ static thread_local
+#define __align__(n) alignas(n)
+// A __device__ variable is an ordinary host object here; its "symbol
+// address" is its address.
+#define HIP_SYMBOL(x) (reinterpret_cast<const void*>(&(x)))
 
 struct dim3 {
   unsigned x, y, z;
@@ -61,6 +65,10 @@ inline hipError_t hipEventDestroy(hipEvent_t) { return hipSuccess; }
 // workgroup each, so persistent kernels loop over many tiles per workgroup.
 constexpr int kSimtCUs = 2;
 typedef enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount = 1 } hipDeviceAttribute_t;
+inline hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+  *p = const_cast<void*>(symbol);
+  return hipSuccess;
+}
 inline hipError_t hipGetDevice(int* d) {
   *d = 0;
   return hipSuccess;
