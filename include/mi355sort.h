@@ -61,7 +61,8 @@ typedef enum ms_op {
     MS_OP_SORT_PAIRS = 1,
     MS_OP_SORT_SEGMENTED = 2,
     MS_OP_MERGE_RUNS = 3,
-    MS_OP_MERGE_SPLIT = 4
+    MS_OP_MERGE_SPLIT = 4,
+    MS_OP_SORT_STEP = 5
 } ms_op;
 
 /*
@@ -163,6 +164,72 @@ ms_status merge_runs(const void *keys_in, const uint32_t *vals_in, void *keys_ou
 ms_status merge_split(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
                       uint64_t n_total, uint64_t num_parts, ms_key_type kt, void *ws, size_t ws_bytes,
                       void *stream);
+
+/*
+ * Continuous batching of sort requests (the serving form of the method: each
+ * request is a whole list of Section 3.2 sorted on its own).  A request of
+ * n keys is sorted over the phases ms_step_plan reports: 1 phase when n fits
+ * one LDS tile (8,192 keys of 4 bytes, 4,096 of 8 bytes: sorted whole), else
+ * 1 + P phases (P = key bytes): phase 0 reads the keys once for the P 8-bit
+ * digit histograms, phase 1 + p is digit pass p (stable counting scatter by
+ * decoupled look-back over the request's tiles).  One sort_step call is one
+ * step: every request it names runs ITS OWN current phase, so requests at
+ * different phases share the launch; a serving loop admits new requests at
+ * phase 0 at any step boundary and drops a request after its last phase.
+ * After a request's last phase (stream order) keys_out / vals_out hold its
+ * stable ascending sort (equal keys in input order).
+ */
+#define MS_STEP_MAX_REQUESTS 1024
+
+typedef struct ms_step_request {
+    const void *keys_in;       /* the request's n keys (device) */
+    const uint32_t *vals_in;   /* its n values, or NULL for a key-only request */
+    void *keys_out;            /* its result (device); must not overlap keys_in or work */
+    uint32_t *vals_out;        /* NULL exactly when vals_in is NULL */
+    void *work;                /* per-request state (device), ms_step_plan's work_bytes,
+                                  owned by the caller, left alone between the request's
+                                  steps; no initialisation needed; NULL if 0 bytes */
+    uint64_t n;                /* keys, at most 2^30 - 1 */
+    uint32_t phase;            /* the phase to run in this step, 0 .. phases - 1 */
+    uint32_t reserved;         /* 0 */
+} ms_step_request;
+
+/*
+ * Phases (host *phases) and per-request work bytes (host *work_bytes) of a
+ * request of n keys of type kt, with or without values.  n = 0: 0 phases.
+ * Errors: MS_EINVAL for NULL outputs, MS_ENOTSUP for an unknown key type or
+ * n >= 2^30.
+ */
+ms_status ms_step_plan(ms_key_type kt, int has_values, uint64_t n, uint32_t *phases, size_t *work_bytes);
+
+/*
+ * One step: `reqs` is a DEVICE array of num_reqs descriptors (at most
+ * MS_STEP_MAX_REQUESTS; each request at most once), all of key type kt and
+ * all with values (has_values = 1) or all without.  ws is the step's control
+ * block, ms_workspace_size(MS_OP_SORT_STEP, ...) bytes, content irrelevant on
+ * entry; two steps in flight at once must not share it.  Two launches on
+ * `stream` (clear the control block, then one persistent kernel over the
+ * tiles of every request).  A request's phases must run in order, one per
+ * step, on one stream (or otherwise ordered); a descriptor whose phase is
+ * out of range is skipped.  Phases run out of order give an unspecified
+ * order inside the request's buffers, never an access outside them.
+ * Errors: MS_EINVAL for num_reqs > MS_STEP_MAX_REQUESTS, NULL reqs with
+ * num_reqs > 0, or a short ws; MS_ENOTSUP for an unknown key type.
+ */
+ms_status sort_step(const ms_step_request *reqs, uint64_t num_reqs, ms_key_type kt, int has_values, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/*
+ * Achievable HBM bandwidth, measured with this library's own streaming
+ * kernels (16-byte coalesced accesses, 2,048 workgroups): kind 0 reads
+ * `bytes` of src (dst receives one 32-bit word per workgroup: at least 8 KiB),
+ * 1 writes `bytes` of dst, 2 copies src to dst; 3, 4, 5 the same with
+ * non-temporal (streaming) accesses.  bytes must be a multiple of 16.  Not
+ * part of the sort; used to read the sort kernels' rates against the
+ * practical ceiling.  Errors: MS_EINVAL for an unknown kind, a size not a
+ * multiple of 16, or NULL pointers.
+ */
+ms_status ms_hbm_probe(int kind, const void *src, void *dst, size_t bytes, void *stream);
 
 /*
  * sort_keys for callers that cannot allocate device memory: code under HIP

@@ -21,9 +21,13 @@ STATUS_NAMES = {0: "MS_OK", 1: "MS_EINVAL", 2: "MS_ENOMEM", 3: "MS_EDEVICE", 4: 
 MS_KEY_I32, MS_KEY_U32, MS_KEY_U64 = 0, 1, 2
 # ms_op
 MS_OP_SORT_KEYS, MS_OP_SORT_PAIRS, MS_OP_SORT_SEGMENTED, MS_OP_MERGE_RUNS, MS_OP_MERGE_SPLIT = 0, 1, 2, 3, 4
+MS_OP_SORT_STEP = 5
+# continuous batching (sort_step)
+MS_STEP_MAX_REQUESTS = 1024
+MS_STEP_REQUEST_BYTES = 56
 
 EXPORTS = ("ms_workspace_size", "sort_keys", "sort_pairs", "part_offsets", "sort_segmented", "merge_runs",
-           "merge_split", "sort_keys_noalloc", "ms_last_error",
+           "merge_split", "ms_step_plan", "sort_step", "ms_hbm_probe", "sort_keys_noalloc", "ms_last_error",
            "ms_timing_enable", "ms_timing_reset", "ms_timing_read", "ms_tune_set", "ms_tune_get")
 # ms_tune_param
 MS_TUNE_PASS_THREADS = 0
@@ -68,11 +72,15 @@ def lib() -> ctypes.CDLL:
         L.sort_pairs.argtypes = [vp, vp, vp, vp, u64, i32, vp, sz, vp]
         L.part_offsets.argtypes = [u64, u64, vp, vp]
         L.sort_keys_noalloc.argtypes = [vp, vp, u64, i32, vp]
+        L.ms_step_plan.argtypes = [i32, i32, u64, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(sz)]
+        L.sort_step.argtypes = [vp, u64, i32, i32, vp, sz, vp]
+        L.ms_hbm_probe.argtypes = [i32, vp, vp, sz, vp]
         L.sort_segmented.argtypes = [vp, vp, vp, vp, vp, u64, u64, i32, vp, sz, vp]
         L.merge_runs.argtypes = [vp, vp, vp, vp, vp, u64, u64, i32, vp, sz, vp]
         L.merge_split.argtypes = [vp, vp, vp, vp, u64, u64, i32, vp, sz, vp]
         for fn in ("ms_workspace_size", "sort_keys", "sort_pairs", "part_offsets", "sort_segmented", "merge_runs",
-                   "merge_split", "sort_keys_noalloc", "ms_timing_enable", "ms_timing_reset"):
+                   "merge_split", "ms_step_plan", "sort_step", "ms_hbm_probe", "sort_keys_noalloc",
+                   "ms_timing_enable", "ms_timing_reset"):
             getattr(L, fn).restype = i32
         L.ms_last_error.argtypes = []
         L.ms_last_error.restype = ctypes.c_char_p
@@ -102,6 +110,28 @@ def workspace_size(op: int, kt: int, has_values: bool, n_total: int, num_segment
     check(lib().ms_workspace_size(op, kt, int(bool(has_values)), n_total, num_segments, ctypes.byref(out)),
           "ms_workspace_size")
     return out.value
+
+
+def step_plan(kt: int, has_values: bool, n: int):
+    """(phases, per-request work bytes) of a sort_step request of n keys."""
+    ph = ctypes.c_uint32(0)
+    wb = ctypes.c_size_t(0)
+    check(lib().ms_step_plan(kt, int(bool(has_values)), n, ctypes.byref(ph), ctypes.byref(wb)), "ms_step_plan")
+    return int(ph.value), int(wb.value)
+
+
+def _step_request_dtype():
+    import numpy as np
+    return np.dtype([("keys_in", np.uint64), ("vals_in", np.uint64), ("keys_out", np.uint64),
+                     ("vals_out", np.uint64), ("work", np.uint64), ("n", np.uint64), ("phase", np.uint32),
+                     ("reserved", np.uint32)])
+
+
+def __getattr__(name):
+    # STEP_REQUEST_DTYPE: the NumPy layout of ms_step_request (NumPy imported lazily)
+    if name == "STEP_REQUEST_DTYPE":
+        return _step_request_dtype()
+    raise AttributeError(name)
 
 
 def tune_set(param: int, value: int) -> None:

@@ -101,6 +101,9 @@ ms_status ms_workspace_size(ms_op op, ms_key_type kt, int has_values, uint64_t n
     case MS_OP_MERGE_SPLIT:
       *bytes = ms::merge_split_workspace_bytes(kt, has_values != 0, n_total, num_segments);
       return MS_OK;
+    case MS_OP_SORT_STEP:
+      *bytes = ms::step_control_bytes();
+      return MS_OK;
   }
   return fail(MS_ENOTSUP, "unknown op %d", static_cast<int>(op));
 }
@@ -133,6 +136,36 @@ ms_status part_offsets(uint64_t n, uint64_t num_parts, uint64_t* offsets_out, vo
     return fail(MS_EINVAL, "part_offsets: num_parts + 1 boundaries do not fit in 64 bits");
   if (!offsets_out) return fail(MS_EINVAL, "part_offsets: NULL offsets_out");
   return ms::partition_offsets(n, num_parts, offsets_out, static_cast<hipStream_t>(stream));
+}
+
+ms_status ms_step_plan(ms_key_type kt, int has_values, uint64_t n, uint32_t* phases, size_t* work_bytes) {
+  if (!phases || !work_bytes) return fail(MS_EINVAL, "ms_step_plan: NULL output pointer");
+  if (!ms::valid_kt(kt)) return fail(MS_ENOTSUP, "ms_step_plan: unknown key type %d", static_cast<int>(kt));
+  return ms::step_request_plan(kt, has_values != 0, n, phases, work_bytes);
+}
+
+ms_status sort_step(const ms_step_request* reqs, uint64_t num_reqs, ms_key_type kt, int has_values, void* ws,
+                    size_t ws_bytes, void* stream) {
+  if (!ms::valid_kt(kt)) return fail(MS_ENOTSUP, "sort_step: unknown key type %d", static_cast<int>(kt));
+  if (num_reqs > MS_STEP_MAX_REQUESTS)
+    return fail(MS_EINVAL, "sort_step: %llu requests in one step, at most %d", static_cast<unsigned long long>(num_reqs),
+                MS_STEP_MAX_REQUESTS);
+  if (num_reqs == 0) return MS_OK;
+  if (!reqs) return fail(MS_EINVAL, "sort_step: NULL request table with %llu requests",
+                         static_cast<unsigned long long>(num_reqs));
+  if (!ws || ws_bytes < ms::step_control_bytes())
+    return fail(MS_EINVAL, "sort_step: workspace too small: %zu bytes given, %zu needed", ws_bytes,
+                ms::step_control_bytes());
+  return ms::sort_step_run(reqs, static_cast<uint32_t>(num_reqs), kt, has_values != 0, ws,
+                           static_cast<hipStream_t>(stream));
+}
+
+ms_status ms_hbm_probe(int kind, const void* src, void* dst, size_t bytes, void* stream) {
+  if (kind < 0 || kind > 5) return fail(MS_EINVAL, "ms_hbm_probe: unknown kind %d", kind);
+  if (bytes % 16) return fail(MS_EINVAL, "ms_hbm_probe: %zu bytes is not a multiple of 16", bytes);
+  const bool reads = kind != 1 && kind != 4;
+  if ((reads && !src) || !dst) return fail(MS_EINVAL, "ms_hbm_probe: NULL pointer");
+  return ms::hbm_probe(kind, src, dst, bytes, static_cast<hipStream_t>(stream));
 }
 
 static ms_status check_ranged(const char* what, const void* keys_in, const uint32_t* vals_in, const void* keys_out,
@@ -222,8 +255,8 @@ ms_status ms_tune_set(ms_tune_param p, int64_t value) {
       ms::g_tune[p] = value;
       return MS_OK;
     case MS_TUNE_SEG_PASSES:
-      if (value != 0 && value != 1)
-        return fail(MS_EINVAL, "MS_TUNE_SEG_PASSES must be 0 or 1 (got %lld)", static_cast<long long>(value));
+      if (value < 0 || value > 2)
+        return fail(MS_EINVAL, "MS_TUNE_SEG_PASSES must be 0, 1 or 2 (got %lld)", static_cast<long long>(value));
       ms::g_tune[p] = value;
       return MS_OK;
     case MS_TUNE_SEG_PASS_THREADS:

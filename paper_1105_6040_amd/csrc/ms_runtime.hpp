@@ -59,6 +59,14 @@ ms_status segsweep_sort(const void* keys_in, const uint32_t* vals_in, void* keys
                         const uint64_t* offsets, uint64_t nseg, uint64_t n, ms_key_type kt, void* ws,
                         size_t ws_bytes, hipStream_t s);
 
+// ---- continuous batching (step.hip) and the bandwidth probe (probe.hip) -----
+size_t step_control_bytes();
+ms_status step_request_plan(ms_key_type kt, bool has_vals, uint64_t n, uint32_t* phases, size_t* work_bytes);
+ms_status sort_step_run(const ms_step_request* reqs, uint32_t num_reqs, ms_key_type kt, bool has_vals, void* ws,
+                        hipStream_t s);
+size_t probe_sink_bytes();
+ms_status hbm_probe(int kind, const void* src, void* dst, size_t bytes, hipStream_t s);
+
 // ---- scatter phase: part boundaries ------------------------------------------
 ms_status partition_offsets(uint64_t n, uint64_t p, uint64_t* off, hipStream_t s);
 

@@ -1025,6 +1025,212 @@ __global__ __launch_bounds__(THREADS) void segsweep_pass_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// 6. The same segment passes as ONE persistent launch: a work queue of
+// (phase, tile) items over the tile table above.  Phase 0 of a segment of
+// several tiles counts its keys for the P digit histograms; phase 1 + p is
+// digit pass p over its tiles (decoupled look-back inside the segment, bases
+// from the segment's histogram).  A segment of one tile is sorted whole in
+// LDS in phase 0 and takes no later phase.  Tickets run phase-major (every
+// tile's phase 0, then every tile's phase 1, ...), so an item only waits for
+// items with earlier tickets -- the previous phase of its own segment (a
+// per-segment count of finished tiles) and, inside a pass, the look-back --
+// and those are already running: no wait can deadlock.  A segment that has
+// finished a phase goes on to the next while others are still in it.
+//
+// Data written in one phase is read in the next by other workgroups, on any
+// XCD, within the same launch: a tile finishes its stores with an
+// agent-scope release fence before counting itself done, and a tile that
+// waited acquires (agent-scope fence) before reading.  Look-back rows: two
+// buffers, pass p in buffer p % 2; phase 0 clears a tile's row in both, and
+// pass p (p >= 1) clears the tile's row of buffer (p + 1) % 2 for pass p + 1,
+// after pass p - 1 of the segment -- the last reader of that row -- is done.
+template <typename K, bool VALS, typename C, typename S>
+__global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
+    const SortPlan* __restrict__ plan, const SegTile* __restrict__ tiles, const uint32_t* __restrict__ num_tiles_p,
+    const uint64_t* __restrict__ off, uint64_t n, K flip, C* __restrict__ seg_hist, uint32_t* __restrict__ done,
+    uint32_t* ticket_ctr, S* status0, S* status1) {
+  constexpr int kThreads = kSegSweepThreads;
+  constexpr int kKpt = PassCfg<kThreads>::kKpt;
+  constexpr int kTile = PassCfg<kThreads>::kTile;
+  constexpr int P = sizeof(K);
+  using St = Status<S>;
+
+  constexpr int kStageBytes = padded16(kTile) * static_cast<int>(sizeof(K));
+  constexpr int kCountBytes = SplitScratch<kThreads>::kCountWords * 4;
+  constexpr int kRawBytes = std::max(std::max(kStageBytes, kCountBytes), P * kRadix * 4);
+  __shared__ __attribute__((aligned(16))) uint8_t s_raw[kRawBytes];
+  K* s_stage = reinterpret_cast<K*>(s_raw);
+  uint32_t* s_counts = reinterpret_cast<uint32_t*>(s_raw);
+  uint32_t* s_h = reinterpret_cast<uint32_t*>(s_raw);  // phase 0: P x kRadix counters
+  __shared__ uint32_t s_vstage[VALS ? padded16(kTile) : 1];
+  __shared__ uint32_t s_hist[kRadix];
+  __shared__ C s_doff[kRadix];
+  __shared__ uint32_t s_scan[kThreads / kWave];
+  __shared__ C s_cscan[kRadix / kWave];
+  __shared__ C s_cscan2[kRadix / kWave];
+  __shared__ uint32_t s_ticket;
+
+  const int tid = threadIdx.x;
+  const uint32_t T = *num_tiles_p;
+  const uint64_t total = static_cast<uint64_t>(P + 1) * T;
+
+  while (true) {
+    if (tid == 0) s_ticket = atomicAdd(ticket_ctr, 1u);
+    __syncthreads();
+    const uint64_t ticket = s_ticket;
+    if (ticket >= total) break;
+    const uint32_t phase = static_cast<uint32_t>(ticket / T);
+    const uint32_t i = static_cast<uint32_t>(ticket % T);
+    const SegTile r = tiles[i];
+    const uint32_t cnt = r.count & kTileCountMask;
+    const uint64_t tbeg = r.begin;
+    const uint64_t tend = tbeg + cnt;
+    const bool only = (r.count & kTileOnly) != 0;
+    const bool first = (r.count & kTileFirst) != 0;
+
+    if (only) {
+      if (phase == 0) {
+        // The whole segment in one tile: every digit pass in LDS, in place.
+        const K* src = static_cast<const K*>(plan->pass[0].src_k);
+        const uint32_t* srcv = plan->pass[0].src_v;
+        K* dst = static_cast<K*>(plan->pass[P - 1].dst_k);
+        uint32_t* dstv = plan->pass[P - 1].dst_v;
+        K keys[kKpt];
+        uint32_t vals[kKpt];
+        load_tile_keys<K, VALS, uint64_t, kKpt>(as_global(src), as_global(srcv),
+                                                tbeg + static_cast<uint64_t>(tid) * kKpt, tend, ~K(0) ^ flip, keys,
+                                                vals);
+#pragma unroll
+        for (int q = 0; q < kKpt; ++q) keys[q] = flip_key(keys[q], flip);
+        for (int p = 0; p < P; ++p)
+          tile_sort_digit<kThreads, kKpt, VALS>(keys, vals, 8 * p, s_stage, s_vstage, s_counts, s_scan,
+                                                p + 1 < P);
+        for (int e = tid; e < static_cast<int>(cnt); e += kThreads) {
+          dst[tbeg + e] = s_stage[pad16(e)] ^ flip;
+          if constexpr (VALS) dstv[tbeg + e] = s_vstage[pad16(e)];
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+
+    // A tile of a segment of several tiles.
+    const uint32_t seg = r.seg;
+    uint64_t sb;
+    const uint64_t slen = segment_span(off, seg, n, &sb);
+    // The segment's records are consecutive from index i - j (j = this
+    // tile's place in the segment); a table capped by offsets that break the
+    // contract may hold only the first ones, and a phase is complete when
+    // every record present has finished it.
+    const uint32_t j = static_cast<uint32_t>((tbeg - sb) / kTile);
+    const uint64_t seg_tiles = (slen + kTile - 1) / kTile;
+    const uint32_t present = static_cast<uint32_t>(std::min<uint64_t>(seg_tiles, T - (i - j)));
+    uint32_t* const d = done + static_cast<size_t>(seg) * (P + 1);
+    C* const h = seg_hist + static_cast<size_t>(seg) * P * kRadix;
+
+    if (phase == 0) {
+      for (int e = tid; e < kRadix; e += kThreads) {
+        status0[static_cast<size_t>(i) * kRadix + e] = 0;
+        status1[static_cast<size_t>(i) * kRadix + e] = 0;
+      }
+      for (int e = tid; e < P * kRadix; e += kThreads) s_h[e] = 0;
+      __syncthreads();
+      K keys[kKpt];
+      uint32_t unused[kKpt];
+      load_tile_keys<K, false, uint64_t, kKpt>(as_global(static_cast<const K*>(plan->pass[0].src_k)),
+                                               gptr<const uint32_t>(nullptr),
+                                               tbeg + static_cast<uint64_t>(tid) * kKpt, tend, K(0), keys, unused);
+#pragma unroll
+      for (int q = 0; q < kKpt; ++q) {
+        if (static_cast<uint32_t>(tid * kKpt + q) < cnt) {
+          const K k = flip_key(keys[q], flip);
+#pragma unroll
+          for (int p = 0; p < P; ++p) atomicAdd(&s_h[p * kRadix + digit_of(k, 8 * p)], 1u);
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < P * kRadix; e += kThreads)
+        if (s_h[e]) atomic_add_c(&h[e], static_cast<C>(s_h[e]));
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) __hip_atomic_fetch_add(&d[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      continue;
+    }
+
+    // Digit pass p, once the segment's previous phase is complete.
+    const int p = static_cast<int>(phase) - 1;
+    if (tid == 0)
+      while (__hip_atomic_load(&d[p], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < present)
+        __builtin_amdgcn_s_sleep(4);
+    __syncthreads();
+    __threadfence();  // every wave acquires what the previous phase wrote
+
+    S* const cur = (p & 1) ? status1 : status0;
+    if (p >= 1) {
+      S* const later = (p & 1) ? status0 : status1;
+      for (int e = tid; e < kRadix; e += kThreads) later[static_cast<size_t>(i) * kRadix + e] = 0;
+    }
+    const PassPlan& pp = plan->pass[p];
+    const int shift = 8 * p;
+    const gptr<const K> src = as_global(static_cast<const K*>(pp.src_k));
+    const gptr<const uint32_t> src_v = as_global(static_cast<const uint32_t*>(pp.src_v));
+    const gptr<K> dst = as_global(static_cast<K*>(pp.dst_k));
+    const gptr<uint32_t> dst_v = as_global(pp.dst_v);
+    const K in_flip = pp.first ? flip : K(0);
+    const K out_flip = pp.last ? flip : K(0);
+    const K pad = ~K(0) ^ in_flip;
+
+    K keys[kKpt];
+    uint32_t vals[kKpt];
+    load_tile_keys<K, VALS, uint64_t, kKpt>(src, src_v, tbeg + static_cast<uint64_t>(tid) * kKpt, tend, pad, keys,
+                                            vals);
+#pragma unroll
+    for (int q = 0; q < kKpt; ++q) keys[q] = flip_key(keys[q], in_flip);
+    for (int e = tid; e < kRadix; e += kThreads) s_hist[e] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kKpt; ++q)
+      if (static_cast<uint32_t>(tid * kKpt + q) < cnt) atomicAdd(&s_hist[digit_of(keys[q], shift)], 1u);
+    __syncthreads();
+    S* const st = cur + static_cast<size_t>(i) * kRadix + tid;
+    uint32_t tcnt = 0;
+    if (tid < kRadix) {
+      tcnt = s_hist[tid];
+      status_store(st, (first ? St::kInc : St::kAgg) | static_cast<S>(tcnt));
+    }
+    tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift, s_stage, s_vstage, s_counts, s_scan, true);
+    S pred = 0;
+    if (tid < kRadix && !first) pred = status_load(st - kRadix);
+    tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift + kSubBits, s_stage, s_vstage, s_counts, s_scan, false);
+    C tile_total, seg_total;
+    const C start = block_exclusive_scan_radix<kThreads>(static_cast<C>(tcnt), s_cscan, &tile_total);
+    const C hc = tid < kRadix ? h[p * kRadix + tid] : C(0);
+    const C base = block_exclusive_scan_radix<kThreads>(hc, s_cscan2, &seg_total);
+    if (tid < kRadix) {
+      C excl = 0;
+      if (!first) {
+        excl = (pred & St::kFlagMask) == St::kInc ? static_cast<C>(pred & St::kValMask)
+                                                  : lookback<C, S, 16>(st, i, kRadix);
+        status_store(st, St::kInc | static_cast<S>(excl + tcnt));
+      }
+      s_doff[tid] = static_cast<C>(sb) + base + excl - start;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int e = tid; e < static_cast<int>(cnt); e += kThreads) {
+      const K k = s_stage[pad16(e)];
+      uint64_t o = static_cast<uint64_t>(s_doff[digit_of(k, shift)]) + static_cast<uint64_t>(e);
+      o = o < n ? o : n - 1;
+      dst[o] = k ^ out_flip;
+      if constexpr (VALS) dst_v[o] = s_vstage[pad16(e)];
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(&d[p + 1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // 4. copy n results when the plan asks for it.
 template <typename K, bool VALS>
 __global__ __launch_bounds__(256) void plan_copy_kernel(const SortPlan* __restrict__ plan, uint64_t n) {
@@ -1236,8 +1442,8 @@ ms_status dispatch(const void* kin, const uint32_t* vin, void* kout, uint32_t* v
 // ---------------------------------------------------------------------------
 // Segmented digit passes (long segments).
 struct SegSweepLayout {
-  size_t plan = 0, ctrs = 0, hist = 0, base = 0, chunks = 0, records = 0, status0 = 0, status1 = 0, alt_k = 0,
-         alt_v = 0, total = 0;
+  size_t plan = 0, ctrs = 0, hist = 0, done = 0, base = 0, chunks = 0, records = 0, status0 = 0, status1 = 0,
+         alt_k = 0, alt_v = 0, total = 0;
   size_t ctrs_hist_bytes = 0, status_bytes = 0;
   uint64_t tiles = 0;  // bound on the tile count: every segment adds at most one partial tile
   uint32_t num_chunks = 0;
@@ -1262,6 +1468,8 @@ SegSweepLayout segsweep_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64
   off += align_up((2 + kMaxPasses) * sizeof(uint32_t));
   L.hist = off;
   off += align_up(nseg * P * kRadix * cb);
+  L.done = off;  // one-launch path: finished tiles per (segment, phase)
+  off += align_up(nseg * (P + 1) * sizeof(uint32_t));
   L.ctrs_hist_bytes = off - L.ctrs;
   L.base = off;
   off += align_up(nseg * P * kRadix * cb);
@@ -1355,9 +1563,55 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   return MS_OK;
 }
 
+// The segment passes as one persistent launch (segqueue_kernel), after the
+// same clearing and planning launches.  Status words are 64-bit when the
+// list has 2^30 keys or more (a segment might), 32-bit otherwise.
+template <typename K, bool VALS, typename C, typename S>
+ms_status run_segqueue(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
+                       uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
+  constexpr uint32_t kTile = SegSweepCfg::kTile;
+  SortPlan* plan = reinterpret_cast<SortPlan*>(ws + L.plan);
+  uint32_t* ctrs = reinterpret_cast<uint32_t*>(ws + L.ctrs);
+  C* hist = reinterpret_cast<C*>(ws + L.hist);
+  uint32_t* done = reinterpret_cast<uint32_t*>(ws + L.done);
+  uint64_t* chunk_start = reinterpret_cast<uint64_t*>(ws + L.chunks);
+  SegTile* records = reinterpret_cast<SegTile*>(ws + L.records);
+  uint32_t* wide = ctrs + 1 + kMaxPasses;
+  // Counters, histograms and done counts only: a tile clears its own
+  // look-back rows before they are used.
+  MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), L.ctrs_hist_bytes / 16,
+            static_cast<uint4*>(nullptr), size_t(0));
+  Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
+  const uint32_t max_tiles = static_cast<uint32_t>(L.tiles);
+  if (L.num_chunks == 1) {
+    MS_LAUNCH("segsweep_plan", (segsweep_plan1_kernel<K, VALS>), 1, kSegPlanThreads, s, off, nseg, n, kTile,
+              max_tiles, wide, ctrs, records, plan, buf);
+  } else {
+    MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile, wide,
+              chunk_start);
+    MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, kSegPlanThreads, s, chunk_start, L.num_chunks,
+              max_tiles, ctrs, plan, buf);
+    MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile,
+              static_cast<const uint64_t*>(chunk_start), max_tiles, wide, records);
+  }
+  const uint64_t blocks = std::min<uint64_t>(
+      (static_cast<uint64_t>(sizeof(K)) + 1) * L.tiles,
+      resident_blocks(reinterpret_cast<const void*>(&segqueue_kernel<K, VALS, C, S>), kSegSweepThreads, 256));
+  MS_LAUNCH("segqueue", (segqueue_kernel<K, VALS, C, S>), static_cast<uint32_t>(blocks), kSegSweepThreads, s,
+            static_cast<const SortPlan*>(plan), static_cast<const SegTile*>(records),
+            static_cast<const uint32_t*>(ctrs), off, n, flip, hist, done, ctrs + 1, reinterpret_cast<S*>(ws + L.status0),
+            reinterpret_cast<S*>(ws + L.status1));
+  return MS_OK;
+}
+
 template <typename K, bool VALS>
 ms_status segsweep_dispatch(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
                             uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
+  // MS_TUNE_SEG_PASSES = 2: all phases in one persistent launch.
+  if (tune_get(MS_TUNE_SEG_PASSES) == 2) {
+    if (L.big) return run_segqueue<K, VALS, uint64_t, uint64_t>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+    return run_segqueue<K, VALS, uint32_t, uint32_t>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+  }
   // 16,384-key tiles only where 1,024 threads fit their registers without
   // spilling: 32-bit keys without values.
   if constexpr (sizeof(K) == 4 && !VALS) {

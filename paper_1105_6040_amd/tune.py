@@ -13,9 +13,10 @@ Tuned per class:
                     comparison network -- bitonic, one wave -- or by radix
                     passes) and, for segments averaging more than 8,192
                     keys, the whole-device segment passes (pass tile: 512
-                    or 1,024 threads x 16 keys) as further candidates
-  serving           the request length above which a request is launched on
-                    its own instead of inside a segmented batch
+                    or 1,024 threads x 16 keys; a launch per phase, or every
+                    phase in one persistent launch) as further candidates
+  serving           the continuous-batching server's bound on steps queued
+                    on the device ahead of the one running
 
 The radix width is fixed at 8 bits (each digit ordered by two 4-bit splits),
 so it is not a tuning dimension.
@@ -42,7 +43,7 @@ SEG_PASS_THREADS = (512, 1024)
 # sort_segmented runs whole-device digit passes when there are several
 # segments averaging more than this many keys (mi355sort.h).
 SEG_PASS_MIN_AVERAGE = 8192
-SERVE_THRESHOLDS = (1 << 13, 1 << 16, 1 << 18)
+SERVE_STEPS_INFLIGHT = (1, 2, 3)
 
 
 def uses_segment_passes(n: int, nseg: int) -> bool:
@@ -161,7 +162,8 @@ class Tuner:
         persistent = [(0, SEG_PASS_THREADS[0], b, m) for b, m in itertools.product(SEG_BLOCKS, SMALL_SORT)]
         space = persistent
         if uses_segment_passes(n, nseg):
-            space = [(1, t, 0, SMALL_SORT[0]) for t in SEG_PASS_THREADS] + persistent
+            space = ([(2, SEG_PASS_THREADS[0], 0, SMALL_SORT[0])] +
+                     [(1, t, 0, SMALL_SORT[0]) for t in SEG_PASS_THREADS] + persistent)
 
         def apply(p):
             N.tune_set(N.MS_TUNE_SEG_PASSES, p[0])
@@ -169,22 +171,23 @@ class Tuner:
             N.tune_set(N.MS_TUNE_SEG_BLOCKS, p[2])
             N.tune_set(N.MS_TUNE_SMALL_SORT, p[3])
 
-        return self._search(key + "|v2", space, apply, run, force)
+        return self._search(key + "|v3", space, apply, run, force)
 
     def tune_serving(self, run_server: Callable[[int], "object"], force: bool = False,
-                     thresholds: Iterable[int] = SERVE_THRESHOLDS) -> dict:
-        """Pick the serving long-request threshold with the lowest p99 latency;
-        run_server(threshold) must run a short trace and return ServeStats."""
-        key = f"{self._device()}|serving"
+                     candidates: Iterable[int] = SERVE_STEPS_INFLIGHT) -> dict:
+        """Pick the continuous-batching server's bound on queued steps with the
+        lowest p99 latency; run_server(steps) must run a short trace (not the
+        one that is reported) and return ServeStats."""
+        key = f"{self._device()}|serving|steps"
         if not force and key in self.cache:
             return self.cache[key]
         trials = []
-        for t in thresholds:
-            st = run_server(t)
-            trials.append((st.p99_ms, st.p50_ms, t))
+        for c in candidates:
+            st = run_server(c)
+            trials.append((st.p99_ms, st.p50_ms, c))
         trials.sort()
         rec = {"params": [trials[0][2]], "p99_ms": round(trials[0][0], 4),
-               "trials": [[t, round(p99, 4), round(p50, 4)] for p99, p50, t in trials]}
+               "trials": [[c, round(p99, 4), round(p50, 4)] for p99, p50, c in trials]}
         self.cache[key] = rec
         self._save()
         return rec

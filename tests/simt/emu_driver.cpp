@@ -174,6 +174,83 @@ static void run_merge(int kt, const std::vector<uint64_t>& lengths) {
   if (!ok) ++failures;
 }
 
+// Continuous batching: requests of the given lengths join the step loop at
+// the given steps (arrival step per request) and every step advances each
+// active request by one phase (sort_step); each result against the oracle.
+template <typename K>
+static void run_steps(int kt, const std::vector<uint64_t>& lengths, const std::vector<int>& arrive, bool pairs,
+                      const char* dist) {
+  const size_t m = lengths.size();
+  std::vector<std::vector<K>> kin(m), kout(m), kexp(m);
+  std::vector<std::vector<uint32_t>> vin(m), vout(m), vexp(m);
+  std::vector<std::vector<char>> work(m);
+  std::vector<uint32_t> phases(m), phase(m, 0);
+  for (size_t i = 0; i < m; ++i) {
+    std::vector<uint64_t> bits;
+    fill(bits, kt, lengths[i], dist);
+    kin[i] = narrow<K>(bits);
+    kout[i].assign(lengths[i], K(0));
+    kexp[i].assign(lengths[i], K(0));
+    vin[i].resize(lengths[i]);
+    for (size_t j = 0; j < lengths[i]; ++j) vin[i][j] = static_cast<uint32_t>(j * 3 + i);
+    vout[i].assign(lengths[i], 0);
+    vexp[i].assign(lengths[i], 0);
+    oracle_sort(kt, kin[i].data(), pairs ? vin[i].data() : nullptr, kexp[i].data(), pairs ? vexp[i].data() : nullptr,
+                lengths[i]);
+    size_t wb = 0;
+    if (ms_step_plan((ms_key_type)kt, pairs, lengths[i], &phases[i], &wb) != MS_OK) {
+      printf("FAIL ms_step_plan: %s\n", ms_last_error());
+      ++failures;
+      return;
+    }
+    work[i].assign(wb + 1, char(0x5a));  // garbage: the histogram phase must clear what it uses
+  }
+  size_t wsb = 0;
+  ms_workspace_size(MS_OP_SORT_STEP, (ms_key_type)kt, pairs, 0, MS_STEP_MAX_REQUESTS, &wsb);
+  std::vector<char> ws(wsb, char(0x33));
+  bool ok = true;
+  int steps = 0;
+  for (int step = 0; step < 1000; ++step) {
+    std::vector<ms_step_request> table;
+    for (size_t i = 0; i < m; ++i) {
+      if (arrive[i] > step || phase[i] >= phases[i]) continue;
+      ms_step_request r = {};
+      r.keys_in = kin[i].data();
+      r.vals_in = pairs ? vin[i].data() : nullptr;
+      r.keys_out = kout[i].data();
+      r.vals_out = pairs ? vout[i].data() : nullptr;
+      r.work = work[i].data();
+      r.n = lengths[i];
+      r.phase = phase[i]++;
+      table.push_back(r);
+    }
+    bool pending = false;
+    for (size_t i = 0; i < m; ++i) pending |= phase[i] < phases[i];
+    if (table.empty() && !pending) break;
+    if (table.empty()) continue;
+    ++steps;
+    ms_status st = sort_step(table.data(), table.size(), (ms_key_type)kt, pairs, ws.data(), ws.size(), nullptr);
+    if (st != MS_OK) {
+      printf("FAIL sort_step: %s\n", ms_last_error());
+      ok = false;
+      break;
+    }
+  }
+  for (size_t i = 0; i < m && ok; ++i) {
+    const bool good = lengths[i] == 0 ||
+                      (memcmp(kout[i].data(), kexp[i].data(), lengths[i] * sizeof(K)) == 0 &&
+                       (!pairs || memcmp(vout[i].data(), vexp[i].data(), lengths[i] * 4) == 0));
+    if (!good) {
+      printf("     request %zu (n=%llu) differs from the oracle\n", i, (unsigned long long)lengths[i]);
+      ok = false;
+    }
+  }
+  printf("%s sort_step kt=%d requests=%zu steps=%d pairs=%d dist=%s\n", ok ? "ok  " : "FAIL", kt, m, steps, pairs,
+         dist);
+  fflush(stdout);
+  if (!ok) ++failures;
+}
+
 int main(int argc, char** argv) {
   const std::string what = argc > 1 ? argv[1] : "all";
   if (what == "quick") {  // a few cases per kernel family, for the CPU test suite
@@ -206,6 +283,37 @@ int main(int argc, char** argv) {
     // overlapping segments whose tiles exceed the tile table: both paths
     run_malformed<uint32_t>(MS_KEY_I32, {0, 30000, 10000, 50000, 20000, 60000}, 60000, true, 1);
     run_malformed<uint32_t>(MS_KEY_U32, {0, 15000, 5000, 12000, 3000, 20000}, 20000, false, 1);
+    // the segment passes as one persistent launch (work queue of phases)
+    ms_tune_set(MS_TUNE_SEG_PASSES, 2);
+    run_segmented<uint32_t>(MS_KEY_I32, {8192, 1, 0, 30000, 5, 8193, 100, 16385, 7, 40000}, true, "uniform");
+    run_segmented<uint64_t>(MS_KEY_U64, {3, 8192, 20000, 4097, 0, 1, 16384, 9000, 2, 30000}, false, "few");
+    ms_tune_set(MS_TUNE_SEG_PASSES, 1);
+    // continuous batching: one-tile and multi-tile requests joining at different steps
+    run_steps<uint32_t>(MS_KEY_U32, {20000, 5, 8192, 8193, 1, 30001, 700, 16384}, {0, 0, 1, 1, 2, 2, 5, 7}, true,
+                        "uniform");
+    run_steps<uint32_t>(MS_KEY_I32, {9000, 3, 25000}, {0, 3, 4}, false, "few");
+  }
+  if (what == "segqueue") {
+    ms_tune_set(MS_TUNE_SEG_PASSES, 2);
+    run_segmented<uint32_t>(MS_KEY_I32, {40000, 0, 20000, 1, 50000}, false, "uniform");
+    run_segmented<uint32_t>(MS_KEY_U32, {16384, 16383, 16385, 8191, 8193}, true, "small");
+    run_segmented<uint64_t>(MS_KEY_U64, {70000, 30001}, true, "few");
+    run_segmented<uint32_t>(MS_KEY_I32, {100000}, true, "sorted");
+    run_segmented<uint32_t>(MS_KEY_I32, {8192, 1, 0, 30000, 5, 8193, 100, 16385, 7, 40000}, true, "uniform");
+    run_segmented<uint64_t>(MS_KEY_U64, {3, 8192, 20000, 8191, 0, 1, 16384, 9000, 2, 30000}, false, "few");
+    run_segmented<uint32_t>(MS_KEY_I32, {9000, 16383, 12000, 10000, 15000, 9500, 16000, 11000}, true, "uniform");
+    run_segmented<uint32_t>(MS_KEY_U32, {18599, 3000, 1200, 40000}, true, "low12");
+    run_malformed<uint32_t>(MS_KEY_I32, {0, 30000, 10000, 50000, 20000, 60000}, 60000, true, 2);
+    run_malformed<uint32_t>(MS_KEY_U32, {0, 15000, 5000, 12000, 3000, 20000}, 20000, false, 2);
+    ms_tune_set(MS_TUNE_SEG_PASSES, 1);
+  }
+  if (what == "step") {
+    run_steps<uint32_t>(MS_KEY_U32, {20000, 5, 8192, 8193, 1, 30001, 700, 16384}, {0, 0, 1, 1, 2, 2, 5, 7}, true,
+                        "uniform");
+    run_steps<uint32_t>(MS_KEY_I32, {9000, 3, 25000, 0, 40000}, {0, 3, 4, 4, 9}, false, "few");
+    run_steps<uint32_t>(MS_KEY_U32, {18599, 12000, 9000}, {0, 0, 0}, true, "low12");
+    run_steps<uint64_t>(MS_KEY_U64, {4096, 4097, 8192, 20001, 3}, {0, 1, 2, 3, 3}, true, "uniform");
+    run_steps<uint64_t>(MS_KEY_U64, {9000, 17000}, {0, 2}, false, "small");
   }
   if (what == "manyseg") {  // hundreds of short segments (with lowered thresholds: several planning chunks)
     std::vector<uint64_t> lens;

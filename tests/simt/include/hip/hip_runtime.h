@@ -31,6 +31,11 @@
 // A __device__ variable is an ordinary host object here; its "symbol
 // address" is its address.
 #define HIP_SYMBOL(x) (reinterpret_cast<const void*>(&(x)))
+// Non-temporal accesses are ordinary accesses here.
+template <typename T>
+inline T __builtin_nontemporal_load(const T* p) { return *p; }
+template <typename T>
+inline void __builtin_nontemporal_store(T v, T* p) { *p = v; }
 
 struct dim3 {
   unsigned x, y, z;
@@ -221,6 +226,10 @@ template <typename T>
 inline T atomicOr(T* p, T v) {
   return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST);
 }
+template <typename T>
+inline T atomicXor(T* p, T v) {
+  return __atomic_fetch_xor(p, v, __ATOMIC_SEQ_CST);
+}
 
 #define __HIP_MEMORY_SCOPE_AGENT 0
 #define __HIP_MEMORY_SCOPE_WORKGROUP 0
@@ -232,6 +241,10 @@ inline T __hip_atomic_load(T* p, int, int) {
 template <typename T>
 inline void __hip_atomic_store(T* p, T v, int, int) {
   __atomic_store_n(p, v, __ATOMIC_SEQ_CST);
+}
+template <typename T>
+inline T __hip_atomic_fetch_add(T* p, T v, int, int) {
+  return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
 }
 
 #define hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, ...) \

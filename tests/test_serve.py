@@ -1,4 +1,4 @@
-"""Serving loop logic on the CPU with a fake executor (no GPU)."""
+"""Serving loop logic on the CPU with fake executors (no GPU)."""
 import numpy as np
 import pytest
 
@@ -15,7 +15,7 @@ def test_percentile_nearest_rank():
     assert serve.percentile([3, 1, 2], 50) == 2
 
 
-def _trace(nreq=150, lo=10, hi=6000, rate=20000.0, seed=3):
+def _trace(nreq=150, lo=10, hi=60000, rate=20000.0, seed=3):
     arr, lengths = inputs.serving_trace(seed=seed, nreq=nreq, lo=lo, hi=hi, rate_per_s=rate)
     reqs = serve.make_requests(arr, lengths)
     total = sum(r.n for r in reqs)
@@ -29,53 +29,77 @@ def _oracle_sort(k, v):
     return oracle.sort(k, v)
 
 
-@pytest.mark.parametrize("batching", [True, False])
-def test_every_request_sorted_alone_and_in_the_mix(batching):
-    reqs, keys, vals = _trace()
-    ex = serve.FakeExecutor(keys, vals, _oracle_sort)
-    stats = serve.Server(ex, budget_bytes=1 << 30, batching=batching, large_threshold=3000,
-                         max_batch_pairs=20000).run(reqs)
-    assert len(stats.latencies_ms) == len(reqs)
+def _check_results(reqs, ex, keys, vals):
     for r in reqs:
         a, b = r.offset, r.offset + r.n
         ek, ev = oracle.sort(keys[a:b], vals[a:b])
-        assert np.array_equal(ex.out_k[a:b], ek) and np.array_equal(ex.out_v[a:b], ev)
+        assert np.array_equal(ex.out_k[a:b], ek) and np.array_equal(ex.out_v[a:b], ev), r.rid
         assert r.done >= r.launched >= r.arrival
-    if batching:
-        assert stats.launches < len(reqs)
-        assert any(r.path == "batch" for r in reqs)
-        assert all(r.path == "single" for r in reqs if r.n > 3000)
-    else:
-        assert stats.launches == len(reqs)
 
 
-def test_fifo_launch_order():
-    reqs, keys, vals = _trace(nreq=80)
+def test_step_server_sorts_every_request():
+    reqs, keys, vals = _trace()
+    ex = serve.FakeStepExecutor(keys, vals, _oracle_sort, small=5000)
+    stats = serve.StepServer(ex, budget_bytes=1 << 30).run(reqs)
+    assert len(stats.latencies_ms) == len(reqs)
+    _check_results(reqs, ex, keys, vals)
+    assert all(r.path == "step" for r in reqs)
+    assert stats.launches < 5 * len(reqs)
+
+
+def test_step_server_runs_every_phase_once_in_order():
+    """Each request appears in consecutive steps, phase 0, 1, ... its last,
+    once each: requests join at a pass boundary and leave after their last."""
+    reqs, keys, vals = _trace(nreq=60, rate=5e4)
+    ex = serve.FakeStepExecutor(keys, vals, _oracle_sort, small=5000)
+    serve.StepServer(ex, budget_bytes=1 << 30, max_steps_inflight=3).run(reqs)
+    seen = {}
+    for k, step in enumerate(ex.phase_log):
+        for rid, ph in step:
+            seen.setdefault(rid, []).append((k, ph))
+    for r in reqs:
+        steps = seen[r.rid]
+        assert [ph for _, ph in steps] == list(range(r.phases)), r.rid
+        assert [k for k, _ in steps] == list(range(steps[0][0], steps[0][0] + r.phases)), r.rid
+    # the batch really mixes phases
+    assert any(len({ph for _, ph in step}) > 1 for step in ex.phase_log)
+
+
+def test_step_server_admits_by_the_hbm_budget():
+    reqs, keys, vals = _trace(nreq=120, rate=1e6)  # everything arrives at once
+    ex = serve.FakeStepExecutor(keys, vals, _oracle_sort, seconds_per_pair=2e-8, small=5000)
+    budget = 3 * 8 * 60000
+    stats = serve.StepServer(ex, budget_bytes=budget).run(reqs)
+    biggest = max(ex.plan(r.n)[1] for r in reqs)
+    assert stats.max_reserved_bytes <= max(budget, biggest)
+    assert stats.budget_waits > 0
+    _check_results(reqs, ex, keys, vals)
+
+
+def test_step_server_slot_limit():
+    reqs, keys, vals = _trace(nreq=100, rate=1e6)
+    ex = serve.FakeStepExecutor(keys, vals, _oracle_sort, small=5000)
+    stats = serve.StepServer(ex, budget_bytes=1 << 40, max_active=7).run(reqs)
+    assert stats.max_active <= 7
+    assert max(len(s) for s in ex.phase_log) <= 7
+    _check_results(reqs, ex, keys, vals)
+
+
+def test_one_launch_per_request_server():
+    reqs, keys, vals = _trace()
     ex = serve.FakeExecutor(keys, vals, _oracle_sort)
-    serve.Server(ex, budget_bytes=1 << 30, batching=True, large_threshold=3000).run(reqs)
+    stats = serve.Server(ex, budget_bytes=1 << 30).run(reqs)
+    assert stats.launches == len(reqs)
+    _check_results(reqs, ex, keys, vals)
     launched = [r.launched for r in sorted(reqs, key=lambda r: r.arrival)]
     assert all(a <= b for a, b in zip(launched, launched[1:]))
 
 
-def test_admission_respects_the_hbm_budget():
-    reqs, keys, vals = _trace(nreq=120, rate=1e6)  # everything arrives at once
+def test_one_launch_server_respects_the_budget():
+    reqs, keys, vals = _trace(nreq=120, rate=1e6)
     ex = serve.FakeExecutor(keys, vals, _oracle_sort, seconds_per_pair=2e-8)
-    budget = 20000 * ex.ws_per_pair  # room for two or three launches at a time
-    stats = serve.Server(ex, budget_bytes=budget, batching=True, large_threshold=3000, max_batch_pairs=8000,
-                         max_inflight=8).run(reqs)
-    biggest_unit = max(ex.workspace_bytes(r.n, 1) for r in reqs)
-    assert stats.max_reserved_bytes <= max(budget, biggest_unit)
+    budget = 20000 * ex.ws_per_pair
+    stats = serve.Server(ex, budget_bytes=budget, max_inflight=8).run(reqs)
+    biggest = max(ex.workspace_bytes(r.n) for r in reqs)
+    assert stats.max_reserved_bytes <= max(budget, biggest)
     assert stats.budget_waits > 0
-
-
-def test_consecutive_only_batches():
-    reqs = serve.make_requests([0.0] * 6, [10, 10, 5000, 10, 10, 10])
-    srv = serve.Server(serve.FakeExecutor(np.zeros(5050, np.uint32), np.zeros(5050, np.uint32), _oracle_sort),
-                       budget_bytes=1 << 30, large_threshold=1000)
-    import collections
-    q = collections.deque(reqs)
-    assert [r.rid for r in srv._next_unit(q)] == [0, 1]
-    q.popleft(); q.popleft()
-    assert [r.rid for r in srv._next_unit(q)] == [2]
-    q.popleft()
-    assert [r.rid for r in srv._next_unit(q)] == [3, 4, 5]
