@@ -277,9 +277,14 @@ const char *ms_last_error(void);
  *                         sorts use 512.
  *   MS_TUNE_SEG_PASSES    1 (the default): sort_segmented runs whole-device
  *                         digit passes when the segments average more than
- *                         8,192 keys; 0: every sort_segmented call is one
- *                         launch of the persistent kernel, whose workgroups
- *                         each take whole segments.
+ *                         8,192 keys, one launch per phase; 2: the same
+ *                         phases as one persistent launch (a work queue of
+ *                         (phase, tile) items, each segment moving to its
+ *                         next phase as soon as its previous one is done),
+ *                         after the planning launches; 0: every
+ *                         sort_segmented call is one launch of the
+ *                         persistent kernel, whose workgroups each take
+ *                         whole segments.
  * ms_tune_set returns MS_EINVAL for an unknown parameter or value;
  * ms_tune_get returns the current value (0 for an unknown parameter).
  */

@@ -141,8 +141,9 @@ def test_tune_parameter_checks():
     assert lib.ms_tune_set(N.MS_TUNE_PASS_THREADS, 300) == N.MS_EINVAL
     assert lib.ms_tune_set(N.MS_TUNE_SMALL_SORT, 32) == N.MS_EINVAL
     old = get(N.MS_TUNE_SEG_PASSES)
-    assert old in (0, 1)
-    assert lib.ms_tune_set(N.MS_TUNE_SEG_PASSES, 2) == N.MS_EINVAL
+    assert old in (0, 1, 2)
+    assert lib.ms_tune_set(N.MS_TUNE_SEG_PASSES, 3) == N.MS_EINVAL
+    assert lib.ms_tune_set(N.MS_TUNE_SEG_PASSES, -1) == N.MS_EINVAL
     assert get(N.MS_TUNE_SEG_PASSES) == old
     assert lib.ms_tune_set(6, 1) == N.MS_EINVAL  # MS_TUNE_COUNT is no parameter
     assert get(6) == 0
