@@ -14,7 +14,7 @@ namespace ms {
 namespace {
 
 constexpr int kProbeThreads = 256;
-constexpr int kProbeUnroll = 4;
+constexpr int kProbeUnroll = 8;
 constexpr int kWaveSize = 64;
 constexpr uint32_t kProbeBlocks = 2048;  // 8 workgroups per compute unit
 
@@ -44,28 +44,34 @@ __device__ __forceinline__ void st16(uint4* p, uint4 v) {
   }
 }
 
-// kind: 0 read, 1 write, 2 copy.  n16 = number of 16-byte words.
+// kind: 0 read, 1 write, 2 copy.  n16 = number of 16-byte words.  Each
+// workgroup streams one contiguous chunk (DRAM pages stay open), 256 threads
+// x kProbeUnroll independent 16-byte accesses in flight per step.
 template <int KIND, bool NT>
 __global__ __launch_bounds__(kProbeThreads) void probe_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                                               size_t n16, uint32_t* __restrict__ sink) {
-  const size_t stride = static_cast<size_t>(gridDim.x) * kProbeThreads;
-  size_t i = static_cast<size_t>(blockIdx.x) * kProbeThreads + threadIdx.x;
+  constexpr size_t kStep = static_cast<size_t>(kProbeThreads) * kProbeUnroll;
+  const size_t per_block = (n16 + gridDim.x - 1) / gridDim.x;
+  const size_t chunk = (per_block + kStep - 1) / kStep * kStep;
+  const size_t begin = static_cast<size_t>(blockIdx.x) * chunk;
+  const size_t end = begin + chunk < n16 ? begin + chunk : n16;
   uint32_t acc = 0;
   const uint4 pattern = make_uint4(0x9e3779b9u, 0x7f4a7c15u, 0x85ebca6bu, 0xc2b2ae35u);
-  for (; i + (kProbeUnroll - 1) * stride < n16; i += kProbeUnroll * stride) {
+  size_t i = begin + threadIdx.x;
+  for (; i + (kProbeUnroll - 1) * kProbeThreads < end; i += kStep) {
     uint4 v[kProbeUnroll];
     if constexpr (KIND != 1) {
 #pragma unroll
-      for (int u = 0; u < kProbeUnroll; ++u) v[u] = ld16<NT>(src + i + u * stride);
+      for (int u = 0; u < kProbeUnroll; ++u) v[u] = ld16<NT>(src + i + u * kProbeThreads);
     }
 #pragma unroll
     for (int u = 0; u < kProbeUnroll; ++u) {
       if constexpr (KIND == 0) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
-      if constexpr (KIND == 1) st16<NT>(dst + i + u * stride, pattern);
-      if constexpr (KIND == 2) st16<NT>(dst + i + u * stride, v[u]);
+      if constexpr (KIND == 1) st16<NT>(dst + i + u * kProbeThreads, pattern);
+      if constexpr (KIND == 2) st16<NT>(dst + i + u * kProbeThreads, v[u]);
     }
   }
-  for (; i < n16; i += stride) {
+  for (; i < end; i += kProbeThreads) {
     if constexpr (KIND == 0) {
       const uint4 v = ld16<NT>(src + i);
       acc ^= v.x ^ v.y ^ v.z ^ v.w;

@@ -587,6 +587,10 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
 // 16,384 keys (1,024 threads; a tunable).  The tile size is an argument of
 // the planning kernels and a template parameter of the pass.
 constexpr int kSegSweepThreads = 512;
+// Workspace words of the one-launch path's queue table and of one segment's
+// finished-tile counts (see segqueue_kernel).
+constexpr size_t kQWordsAll = 512;
+constexpr size_t kDoneWords = 32;
 // Used when the segments average more keys than one workgroup sorts in LDS
 // (8,192): shorter ones are sorted faster by one workgroup each.
 constexpr uint64_t kSegSweepMinAverage = 8192;
@@ -1026,29 +1030,215 @@ __global__ __launch_bounds__(THREADS) void segsweep_pass_kernel(
 
 // ---------------------------------------------------------------------------
 // 6. The same segment passes as ONE persistent launch: a work queue of
-// (phase, tile) items over the tile table above.  Phase 0 of a segment of
-// several tiles counts its keys for the P digit histograms; phase 1 + p is
-// digit pass p over its tiles (decoupled look-back inside the segment, bases
-// from the segment's histogram).  A segment of one tile is sorted whole in
-// LDS in phase 0 and takes no later phase.  Tickets run phase-major (every
-// tile's phase 0, then every tile's phase 1, ...), so an item only waits for
-// items with earlier tickets -- the previous phase of its own segment (a
-// per-segment count of finished tiles) and, inside a pass, the look-back --
-// and those are already running: no wait can deadlock.  A segment that has
-// finished a phase goes on to the next while others are still in it.
+// (phase, tile) items over a tile table like the one above.  Phase 0 of a
+// segment of several tiles counts its keys for the P digit histograms; phase
+// 1 + p is digit pass p over its tiles (decoupled look-back inside the
+// segment, bases from the segment's histogram).  A segment of one tile is
+// sorted whole in LDS in phase 0 and takes no later phase.
 //
-// Data written in one phase is read in the next by other workgroups, on any
-// XCD, within the same launch: a tile finishes its stores with an
-// agent-scope release fence before counting itself done, and a tile that
-// waited acquires (agent-scope fence) before reading.  Look-back rows: two
-// buffers, pass p in buffer p % 2; phase 0 clears a tile's row in both, and
-// pass p (p >= 1) clears the tile's row of buffer (p + 1) % 2 for pass p + 1,
-// after pass p - 1 of the segment -- the last reader of that row -- is done.
+// XCD-aware: the chip's L2 is one cache per XCD, and one XCD's L2 is not
+// kept coherent with another's inside a kernel.  Keys written in one phase
+// are read by other workgroups in the next, so every segment is given to one
+// XCD: segment s goes to queue s % Q, and each queue is claimed by the first
+// workgroup that finds it unclaimed, for the XCD that workgroup runs on (its
+// XCC_ID hardware register); only workgroups of the owning XCD take its
+// tickets.  A workgroup serves a queue its XCD owns while one has tickets
+// left, then claims an unclaimed one, and exits when neither remains, so
+// every queue is served whatever the number of XCDs.  Inside an XCD the L1s are
+// write-through into the shared L2, so a tile publishes a finished phase by
+// waiting for its own stores and counting itself done, and a tile that waited
+// invalidates its CU's L1 before reading -- no L2 write-back or invalidation,
+// which across XCDs would be needed for every tile.  Q is 8 (every XCD) for
+// large inputs and 1 (one XCD, whose L2 then holds the whole working set) for
+// small ones.  Look-back status words and the per-segment histograms are read
+// and written with device-coherent atomics, as in the other passes.
+//
+// Tickets of a queue run phase-major (every tile's phase 0, then every tile's
+// phase 1, ...), so an item only waits for items with earlier tickets of its
+// own queue -- the previous phase of its own segment (a per-segment count of
+// finished tiles) and, inside a pass, the look-back -- which are already
+// running: no wait can deadlock.  Look-back rows: two buffers, pass p in
+// buffer p % 2; phase 0 clears a tile's row in both, and pass p (p >= 1)
+// clears the tile's row of buffer (p + 1) % 2 for pass p + 1, after pass
+// p - 1 of the segment -- the last reader of that row -- is done.
+constexpr int kMaxQueues = 8;
+// The queue table (its own cleared block of the workspace): each queue's
+// ticket counter on a cache line of its own (every workgroup of an XCD takes
+// tickets there), then the queues' record starts, record counts and owners
+// (XCC_ID + 1, 0 = unclaimed).  A segment's finished-tile counts likewise
+// take a cache line per segment: tiles waiting on one segment poll it while
+// tiles of neighbouring segments count themselves done.
+constexpr int kLineWords = 32;
+constexpr int kQTickets = 0;
+constexpr int kQStarts = kMaxQueues * kLineWords;
+constexpr int kQTotals = kQStarts + kMaxQueues;
+constexpr int kQOwners = kQTotals + kMaxQueues;
+constexpr int kQWords = kQOwners + kMaxQueues;
+constexpr int kDoneStride = kLineWords;
+static_assert(kDoneStride >= kMaxPasses + 1 && kDoneStride == kDoneWords, "one line of phase counts per segment");
+static_assert(kQWords <= static_cast<int>(kQWordsAll), "queue table fits its block");
+
+__device__ __forceinline__ uint32_t xcc_id() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  uint32_t v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return v & 0xF;
+#else
+  return blockIdx.x % kMaxQueues;  // the dispatch order the register reports on the GPU
+#endif
+}
+
+// Invalidates this CU's vector L1, so that the following loads read what
+// other CUs of the same XCD have written into the shared L2.
+__device__ __forceinline__ void invalidate_l1() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("buffer_inv sc0" ::: "memory");
+#endif
+}
+
+// Tiles of this block's segments for each of the nq queues (segment s in
+// queue s % nq; a thread's kSegPlanPerThread = 8 segments fall in queues
+// i % nq); per queue, the thread's exclusive start in the block and the
+// block's total.
+__device__ __forceinline__ void chunk_queue_tiles(const uint64_t* off, uint32_t nseg, uint64_t n, uint32_t tile,
+                                                  uint32_t nq, uint64_t* s_scan, uint64_t (&start)[kMaxQueues],
+                                                  uint64_t (&total)[kMaxQueues], uint64_t (&mine)[kMaxQueues]) {
+  static_assert(kSegPlanPerThread == kMaxQueues, "one segment of each queue per thread");
+  const uint32_t s0 = blockIdx.x * kSegChunk + threadIdx.x * kSegPlanPerThread;
+#pragma unroll
+  for (int q = 0; q < kMaxQueues; ++q) mine[q] = 0;
+#pragma unroll
+  for (int i = 0; i < kSegPlanPerThread; ++i)
+    if (s0 + i < nseg) {
+      uint64_t b;
+      const uint64_t len = segment_span(off, s0 + i, n, &b);
+      mine[i % nq] += (len + tile - 1) / tile;
+    }
+  for (uint32_t q = 0; q < nq; ++q) {
+    start[q] = block_exclusive_scan_radix<kSegPlanThreads>(mine[q], s_scan, &total[q]);
+    __syncthreads();
+  }
+}
+
+// Plan step 1: per (chunk, queue) tile counts, row c of `counts`.
+__global__ __launch_bounds__(kSegPlanThreads) void segq_count_kernel(const uint64_t* __restrict__ off, uint32_t nseg,
+                                                                    uint64_t n, uint32_t tile, uint32_t nq,
+                                                                    uint64_t* __restrict__ counts) {
+  __shared__ uint64_t s_scan[kRadix / kWave];
+  uint64_t start[kMaxQueues], total[kMaxQueues], mine[kMaxQueues];
+  chunk_queue_tiles(off, nseg, n, tile, nq, s_scan, start, total, mine);
+  if (threadIdx.x < nq) {
+    uint64_t t = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxQueues; ++q)
+      if (q == static_cast<int>(threadIdx.x)) t = total[q];
+    counts[static_cast<size_t>(blockIdx.x) * kMaxQueues + threadIdx.x] = t;
+  }
+}
+
+// Plan step 2 (one block): record starts of every (chunk, queue), queue-major
+// (queue 0's tiles of every chunk, then queue 1's, ...), in place of the
+// counts; the queue table (start and record count of every queue, the table
+// capped at max_tiles) and the pass plan.
+template <typename K, bool VALS>
+__global__ __launch_bounds__(kSegPlanThreads) void segq_plan_kernel(uint64_t* __restrict__ counts, uint32_t chunks,
+                                                                   uint32_t nq, uint32_t max_tiles,
+                                                                   uint32_t* __restrict__ ctrs,
+                                                                   uint32_t* __restrict__ qtab, SortPlan* plan,
+                                                                   Buffers buf) {
+  __shared__ uint64_t s_scan[kRadix / kWave];
+  const int tid = threadIdx.x;
+  uint64_t carry = 0;
+  for (uint32_t q = 0; q < nq; ++q) {
+    if (tid == 0) qtab[kQStarts + q] = static_cast<uint32_t>(carry < max_tiles ? carry : max_tiles);
+    for (uint32_t c0 = 0; c0 < chunks; c0 += kSegPlanThreads) {
+      const uint32_t c = c0 + tid;
+      const uint64_t v = c < chunks ? counts[static_cast<size_t>(c) * kMaxQueues + q] : 0u;
+      uint64_t sum;
+      const uint64_t ex = block_exclusive_scan_radix<kSegPlanThreads>(v, s_scan, &sum);
+      if (c < chunks) counts[static_cast<size_t>(c) * kMaxQueues + q] = carry + ex;
+      carry += sum;
+      __syncthreads();
+    }
+  }
+  if (tid != 0) return;
+  const uint32_t table = static_cast<uint32_t>(carry < max_tiles ? carry : max_tiles);
+  ctrs[0] = table;
+  for (uint32_t q = 0; q < nq; ++q) {
+    const uint32_t b = qtab[kQStarts + q];
+    const uint32_t e = q + 1 < nq ? qtab[kQStarts + q + 1] : table;
+    qtab[kQTotals + q] = e - b;
+  }
+  write_segsweep_plan<K, VALS>(plan, buf);
+}
+
+// Plan step 3: this chunk's records, queue by queue, at the starts step 2
+// wrote; records at max_tiles and beyond are not written.
+__global__ __launch_bounds__(kSegPlanThreads) void segq_fill_kernel(const uint64_t* __restrict__ off, uint32_t nseg,
+                                                                   uint64_t n, uint32_t tile, uint32_t nq,
+                                                                   const uint64_t* __restrict__ starts,
+                                                                   uint32_t max_tiles, SegTile* __restrict__ tiles) {
+  __shared__ uint64_t s_scan[kRadix / kWave];
+  __shared__ uint64_t s_start[kSegPlanThreads + 1];  // per thread: first local tile of its segment of queue q
+  uint64_t start[kMaxQueues], total[kMaxQueues], mine[kMaxQueues];
+  chunk_queue_tiles(off, nseg, n, tile, nq, s_scan, start, total, mine);
+  const uint32_t s0 = blockIdx.x * kSegChunk + threadIdx.x * kSegPlanPerThread;
+  for (uint32_t q = 0; q < nq; ++q) {
+    uint64_t my_start = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxQueues; ++k)
+      if (k == static_cast<int>(q)) {
+        my_start = start[k];
+        tot = total[k];
+      }
+    s_start[threadIdx.x] = my_start;
+    if (threadIdx.x == 0) s_start[kSegPlanThreads] = tot;
+    __syncthreads();
+    const uint64_t base = starts[static_cast<size_t>(blockIdx.x) * kMaxQueues + q];
+    for (uint64_t t = threadIdx.x; t < tot; t += kSegPlanThreads) {
+      if (base + t >= max_tiles) break;
+      // The thread whose queue-q segments hold local tile t: the last one
+      // whose start is <= t (its segment then has a tile at t).
+      uint32_t lo = 0, hi = kSegPlanThreads;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (s_start[mid] <= t)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      // Thread lo's segments of queue q: i = q, q + nq, ... < 8, in order.
+      uint64_t run = s_start[lo];
+      for (uint32_t i = q; i < static_cast<uint32_t>(kSegPlanPerThread); i += nq) {
+        const uint32_t sg = blockIdx.x * kSegChunk + lo * kSegPlanPerThread + i;
+        if (sg >= nseg) break;
+        uint64_t b;
+        const uint64_t len = segment_span(off, sg, n, &b);
+        const uint64_t nt = (len + tile - 1) / tile;
+        if (t < run + nt) {
+          const uint64_t j = t - run;
+          const uint64_t tb = b + j * tile;
+          SegTile r;
+          r.begin = tb;
+          r.count = static_cast<uint32_t>(len - j * tile < tile ? len - j * tile : tile) | (j == 0 ? kTileFirst : 0u) |
+                    (nt == 1 ? kTileOnly : 0u);
+          r.seg = sg;
+          tiles[base + t] = r;
+          break;
+        }
+        run += nt;
+      }
+    }
+    __syncthreads();
+  }
+  (void)s0;
+}
+
 template <typename K, bool VALS, typename C, typename S>
 __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
-    const SortPlan* __restrict__ plan, const SegTile* __restrict__ tiles, const uint32_t* __restrict__ num_tiles_p,
-    const uint64_t* __restrict__ off, uint64_t n, K flip, C* __restrict__ seg_hist, uint32_t* __restrict__ done,
-    uint32_t* ticket_ctr, S* status0, S* status1) {
+    const SortPlan* __restrict__ plan, const SegTile* __restrict__ tiles, const uint32_t* __restrict__ ctrs,
+    uint32_t* __restrict__ qtab, uint32_t nq, const uint64_t* __restrict__ off, uint64_t n, K flip,
+    C* __restrict__ seg_hist, uint32_t* __restrict__ done, S* status0, S* status1) {
   constexpr int kThreads = kSegSweepThreads;
   constexpr int kKpt = PassCfg<kThreads>::kKpt;
   constexpr int kTile = PassCfg<kThreads>::kTile;
@@ -1071,16 +1261,47 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
   __shared__ uint32_t s_ticket;
 
   const int tid = threadIdx.x;
-  const uint32_t T = *num_tiles_p;
-  const uint64_t total = static_cast<uint64_t>(P + 1) * T;
+  const uint32_t me = xcc_id() + 1;
+  uint32_t* const owner = qtab + kQOwners;
+  const uint32_t table = ctrs[0];
+  __shared__ int s_q;
+  int q = -1;  // the queue this workgroup serves (uniform)
 
   while (true) {
-    if (tid == 0) s_ticket = atomicAdd(ticket_ctr, 1u);
+    if (tid == 0) {
+      // The next ticket: from the current queue, else from another queue this
+      // XCD owns that has tickets left, else from a queue this workgroup
+      // claims for its XCD; none: done.
+      uint32_t t = 0;
+      while (true) {
+        if (q >= 0) {
+          const uint32_t tot = (P + 1) * qtab[kQTotals + q];
+          t = atomicAdd(&qtab[kQTickets + q * kLineWords], 1u);
+          if (t < tot) break;
+          q = -1;
+        }
+        for (uint32_t k = 0; k < nq && q < 0; ++k) {
+          const uint32_t tot = (P + 1) * qtab[kQTotals + k];
+          if (__hip_atomic_load(&owner[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == me &&
+              __hip_atomic_load(&qtab[kQTickets + k * kLineWords], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tot)
+            q = static_cast<int>(k);
+        }
+        for (uint32_t k = 0; k < nq && q < 0; ++k)
+          if (__hip_atomic_load(&owner[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
+              atomicCAS(&owner[k], 0u, me) == 0u)
+            q = static_cast<int>(k);
+        if (q < 0) break;
+      }
+      s_q = q;
+      s_ticket = t;
+    }
     __syncthreads();
+    q = s_q;
+    if (q < 0) break;
+    const uint32_t T = qtab[kQTotals + q];
     const uint64_t ticket = s_ticket;
-    if (ticket >= total) break;
     const uint32_t phase = static_cast<uint32_t>(ticket / T);
-    const uint32_t i = static_cast<uint32_t>(ticket % T);
+    const uint32_t i = qtab[kQStarts + q] + static_cast<uint32_t>(ticket % T);
     const SegTile r = tiles[i];
     const uint32_t cnt = r.count & kTileCountMask;
     const uint64_t tbeg = r.begin;
@@ -1101,7 +1322,7 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
                                                 tbeg + static_cast<uint64_t>(tid) * kKpt, tend, ~K(0) ^ flip, keys,
                                                 vals);
 #pragma unroll
-        for (int q = 0; q < kKpt; ++q) keys[q] = flip_key(keys[q], flip);
+        for (int k = 0; k < kKpt; ++k) keys[k] = flip_key(keys[k], flip);
         for (int p = 0; p < P; ++p)
           tile_sort_digit<kThreads, kKpt, VALS>(keys, vals, 8 * p, s_stage, s_vstage, s_counts, s_scan,
                                                 p + 1 < P);
@@ -1114,24 +1335,23 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
       continue;
     }
 
-    // A tile of a segment of several tiles.
+    // A tile of a segment of several tiles.  Its records are consecutive
+    // from index i - j (j = this tile's place in the segment); a table capped
+    // by offsets that break the contract may hold only the first ones, and a
+    // phase is complete when every record present has finished it.
     const uint32_t seg = r.seg;
     uint64_t sb;
     const uint64_t slen = segment_span(off, seg, n, &sb);
-    // The segment's records are consecutive from index i - j (j = this
-    // tile's place in the segment); a table capped by offsets that break the
-    // contract may hold only the first ones, and a phase is complete when
-    // every record present has finished it.
     const uint32_t j = static_cast<uint32_t>((tbeg - sb) / kTile);
     const uint64_t seg_tiles = (slen + kTile - 1) / kTile;
-    const uint32_t present = static_cast<uint32_t>(std::min<uint64_t>(seg_tiles, T - (i - j)));
-    uint32_t* const d = done + static_cast<size_t>(seg) * (P + 1);
+    const uint32_t present = static_cast<uint32_t>(std::min<uint64_t>(seg_tiles, table - (i - j)));
+    uint32_t* const d = done + static_cast<size_t>(seg) * kDoneStride;
     C* const h = seg_hist + static_cast<size_t>(seg) * P * kRadix;
 
     if (phase == 0) {
       for (int e = tid; e < kRadix; e += kThreads) {
-        status0[static_cast<size_t>(i) * kRadix + e] = 0;
-        status1[static_cast<size_t>(i) * kRadix + e] = 0;
+        status_store(&status0[static_cast<size_t>(i) * kRadix + e], S(0));
+        status_store(&status1[static_cast<size_t>(i) * kRadix + e], S(0));
       }
       for (int e = tid; e < P * kRadix; e += kThreads) s_h[e] = 0;
       __syncthreads();
@@ -1141,34 +1361,42 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
                                                gptr<const uint32_t>(nullptr),
                                                tbeg + static_cast<uint64_t>(tid) * kKpt, tend, K(0), keys, unused);
 #pragma unroll
-      for (int q = 0; q < kKpt; ++q) {
-        if (static_cast<uint32_t>(tid * kKpt + q) < cnt) {
-          const K k = flip_key(keys[q], flip);
+      for (int k = 0; k < kKpt; ++k) {
+        if (static_cast<uint32_t>(tid * kKpt + k) < cnt) {
+          const K key = flip_key(keys[k], flip);
 #pragma unroll
-          for (int p = 0; p < P; ++p) atomicAdd(&s_h[p * kRadix + digit_of(k, 8 * p)], 1u);
+          for (int p = 0; p < P; ++p) atomicAdd(&s_h[p * kRadix + digit_of(key, 8 * p)], 1u);
         }
       }
       __syncthreads();
       for (int e = tid; e < P * kRadix; e += kThreads)
         if (s_h[e]) atomic_add_c(&h[e], static_cast<C>(s_h[e]));
-      __threadfence();
+      // Every wave's atomics and stores complete before the tile counts
+      // itself done.
+      __builtin_amdgcn_s_waitcnt(waitcnt_vmcnt(0));
       __syncthreads();
-      if (tid == 0) __hip_atomic_fetch_add(&d[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) __hip_atomic_fetch_add(&d[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       continue;
     }
 
     // Digit pass p, once the segment's previous phase is complete.
     const int p = static_cast<int>(phase) - 1;
-    if (tid == 0)
-      while (__hip_atomic_load(&d[p], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < present)
-        __builtin_amdgcn_s_sleep(4);
+    if (tid == 0) {
+      // Back off while waiting: every poll is a device-coherent read of the
+      // line that finishing tiles count themselves done on.
+      int nap = 1;
+      while (__hip_atomic_load(&d[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < present) {
+        for (int k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(8);
+        nap = nap < 16 ? 2 * nap : 16;
+      }
+    }
     __syncthreads();
-    __threadfence();  // every wave acquires what the previous phase wrote
+    invalidate_l1();  // the previous phase's keys, written by other CUs of this XCD
 
     S* const cur = (p & 1) ? status1 : status0;
     if (p >= 1) {
       S* const later = (p & 1) ? status0 : status1;
-      for (int e = tid; e < kRadix; e += kThreads) later[static_cast<size_t>(i) * kRadix + e] = 0;
+      for (int e = tid; e < kRadix; e += kThreads) status_store(&later[static_cast<size_t>(i) * kRadix + e], S(0));
     }
     const PassPlan& pp = plan->pass[p];
     const int shift = 8 * p;
@@ -1185,12 +1413,12 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
     load_tile_keys<K, VALS, uint64_t, kKpt>(src, src_v, tbeg + static_cast<uint64_t>(tid) * kKpt, tend, pad, keys,
                                             vals);
 #pragma unroll
-    for (int q = 0; q < kKpt; ++q) keys[q] = flip_key(keys[q], in_flip);
+    for (int k = 0; k < kKpt; ++k) keys[k] = flip_key(keys[k], in_flip);
     for (int e = tid; e < kRadix; e += kThreads) s_hist[e] = 0;
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kKpt; ++q)
-      if (static_cast<uint32_t>(tid * kKpt + q) < cnt) atomicAdd(&s_hist[digit_of(keys[q], shift)], 1u);
+    for (int k = 0; k < kKpt; ++k)
+      if (static_cast<uint32_t>(tid * kKpt + k) < cnt) atomicAdd(&s_hist[digit_of(keys[k], shift)], 1u);
     __syncthreads();
     S* const st = cur + static_cast<size_t>(i) * kRadix + tid;
     uint32_t tcnt = 0;
@@ -1204,7 +1432,9 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
     tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift + kSubBits, s_stage, s_vstage, s_counts, s_scan, false);
     C tile_total, seg_total;
     const C start = block_exclusive_scan_radix<kThreads>(static_cast<C>(tcnt), s_cscan, &tile_total);
-    const C hc = tid < kRadix ? h[p * kRadix + tid] : C(0);
+    const C hc = tid < kRadix
+                     ? __hip_atomic_load(&h[p * kRadix + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : C(0);
     const C base = block_exclusive_scan_radix<kThreads>(hc, s_cscan2, &seg_total);
     if (tid < kRadix) {
       C excl = 0;
@@ -1224,9 +1454,9 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
       dst[o] = k ^ out_flip;
       if constexpr (VALS) dst_v[o] = s_vstage[pad16(e)];
     }
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(waitcnt_vmcnt(0));
     __syncthreads();
-    if (tid == 0) __hip_atomic_fetch_add(&d[p + 1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) __hip_atomic_fetch_add(&d[p + 1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -1442,7 +1672,7 @@ ms_status dispatch(const void* kin, const uint32_t* vin, void* kout, uint32_t* v
 // ---------------------------------------------------------------------------
 // Segmented digit passes (long segments).
 struct SegSweepLayout {
-  size_t plan = 0, ctrs = 0, hist = 0, done = 0, base = 0, chunks = 0, records = 0, status0 = 0, status1 = 0,
+  size_t plan = 0, ctrs = 0, hist = 0, qtab = 0, done = 0, base = 0, chunks = 0, records = 0, status0 = 0, status1 = 0,
          alt_k = 0, alt_v = 0, total = 0;
   size_t ctrs_hist_bytes = 0, status_bytes = 0;
   uint64_t tiles = 0;  // bound on the tile count: every segment adds at most one partial tile
@@ -1468,13 +1698,15 @@ SegSweepLayout segsweep_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64
   off += align_up((2 + kMaxPasses) * sizeof(uint32_t));
   L.hist = off;
   off += align_up(nseg * P * kRadix * cb);
-  L.done = off;  // one-launch path: finished tiles per (segment, phase)
-  off += align_up(nseg * (P + 1) * sizeof(uint32_t));
+  L.qtab = off;  // one-launch path: queue table
+  off += align_up(kQWordsAll * sizeof(uint32_t));
+  L.done = off;  // one-launch path: finished tiles per (segment, phase), a cache line per segment
+  off += align_up(nseg * kDoneWords * sizeof(uint32_t));
   L.ctrs_hist_bytes = off - L.ctrs;
   L.base = off;
   off += align_up(nseg * P * kRadix * cb);
-  L.chunks = off;
-  off += align_up(static_cast<size_t>(L.num_chunks) * sizeof(uint64_t));
+  L.chunks = off;  // chunk tile starts; per (chunk, queue) starts for the one-launch path
+  off += align_up(static_cast<size_t>(L.num_chunks) * 8 * sizeof(uint64_t));
   L.records = off;
   off += align_up(static_cast<size_t>(L.tiles) * sizeof(SegTile));
   L.status_bytes = align_up(static_cast<size_t>(L.tiles) * kRadix * cb);
@@ -1564,8 +1796,11 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
 }
 
 // The segment passes as one persistent launch (segqueue_kernel), after the
-// same clearing and planning launches.  Status words are 64-bit when the
-// list has 2^30 keys or more (a segment might), 32-bit otherwise.
+// clearing and planning launches.  Status words are 64-bit when the list has
+// 2^30 keys or more (a segment might), 32-bit otherwise.  Inputs of at most
+// kOneXcdTiles tiles run on one XCD (one queue), larger ones on every XCD.
+constexpr uint64_t kOneXcdTiles = 256;
+
 template <typename K, bool VALS, typename C, typename S>
 ms_status run_segqueue(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
                        uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
@@ -1574,33 +1809,27 @@ ms_status run_segqueue(const void* kin, const uint32_t* vin, void* kout, uint32_
   uint32_t* ctrs = reinterpret_cast<uint32_t*>(ws + L.ctrs);
   C* hist = reinterpret_cast<C*>(ws + L.hist);
   uint32_t* done = reinterpret_cast<uint32_t*>(ws + L.done);
-  uint64_t* chunk_start = reinterpret_cast<uint64_t*>(ws + L.chunks);
+  uint64_t* counts = reinterpret_cast<uint64_t*>(ws + L.chunks);
   SegTile* records = reinterpret_cast<SegTile*>(ws + L.records);
-  uint32_t* wide = ctrs + 1 + kMaxPasses;
+  const uint32_t nq = L.tiles <= kOneXcdTiles ? 1u : static_cast<uint32_t>(kMaxQueues);
   // Counters, histograms and done counts only: a tile clears its own
   // look-back rows before they are used.
   MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), L.ctrs_hist_bytes / 16,
             static_cast<uint4*>(nullptr), size_t(0));
   Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
   const uint32_t max_tiles = static_cast<uint32_t>(L.tiles);
-  if (L.num_chunks == 1) {
-    MS_LAUNCH("segsweep_plan", (segsweep_plan1_kernel<K, VALS>), 1, kSegPlanThreads, s, off, nseg, n, kTile,
-              max_tiles, wide, ctrs, records, plan, buf);
-  } else {
-    MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile, wide,
-              chunk_start);
-    MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, kSegPlanThreads, s, chunk_start, L.num_chunks,
-              max_tiles, ctrs, plan, buf);
-    MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile,
-              static_cast<const uint64_t*>(chunk_start), max_tiles, wide, records);
-  }
-  const uint64_t blocks = std::min<uint64_t>(
-      (static_cast<uint64_t>(sizeof(K)) + 1) * L.tiles,
-      resident_blocks(reinterpret_cast<const void*>(&segqueue_kernel<K, VALS, C, S>), kSegSweepThreads, 256));
+  MS_LAUNCH("segq_plan", segq_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile, nq, counts);
+  uint32_t* qtab = reinterpret_cast<uint32_t*>(ws + L.qtab);
+  MS_LAUNCH("segq_plan", (segq_plan_kernel<K, VALS>), 1, kSegPlanThreads, s, counts, L.num_chunks, nq, max_tiles,
+            ctrs, qtab, plan, buf);
+  MS_LAUNCH("segq_plan", segq_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile, nq,
+            static_cast<const uint64_t*>(counts), max_tiles, records);
+  const uint64_t blocks = resident_blocks(reinterpret_cast<const void*>(&segqueue_kernel<K, VALS, C, S>),
+                                          kSegSweepThreads, 256);
   MS_LAUNCH("segqueue", (segqueue_kernel<K, VALS, C, S>), static_cast<uint32_t>(blocks), kSegSweepThreads, s,
             static_cast<const SortPlan*>(plan), static_cast<const SegTile*>(records),
-            static_cast<const uint32_t*>(ctrs), off, n, flip, hist, done, ctrs + 1, reinterpret_cast<S*>(ws + L.status0),
-            reinterpret_cast<S*>(ws + L.status1));
+            static_cast<const uint32_t*>(ctrs), qtab, nq, off, n, flip, hist, done,
+            reinterpret_cast<S*>(ws + L.status0), reinterpret_cast<S*>(ws + L.status1));
   return MS_OK;
 }
 

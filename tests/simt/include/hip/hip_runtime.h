@@ -230,6 +230,11 @@ template <typename T>
 inline T atomicXor(T* p, T v) {
   return __atomic_fetch_xor(p, v, __ATOMIC_SEQ_CST);
 }
+template <typename T>
+inline T atomicCAS(T* p, T expected, T desired) {
+  __atomic_compare_exchange_n(p, &expected, desired, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
+  return expected;  // the old value
+}
 
 #define __HIP_MEMORY_SCOPE_AGENT 0
 #define __HIP_MEMORY_SCOPE_WORKGROUP 0

@@ -398,6 +398,35 @@ def test_sort_segmented_many_long_segments(nseg, nlong, threads):
         N.tune_set(N.MS_TUNE_SEG_PASS_THREADS, old)
 
 
+@pytest.mark.parametrize("dt", ["i32", "u32", "u64"])
+@pytest.mark.parametrize("nseg,nlong", [(7, 5), (1025, 60), (2049, 130), (4700, 320)])
+def test_sort_segmented_work_queue(dt, nseg, nlong):
+    """MS_TUNE_SEG_PASSES = 2: every phase of the segment passes (histogram,
+    P digit passes; one-tile segments sorted whole) in one persistent launch,
+    each segment going on to its next phase as soon as its previous one is
+    done.  Keys and pairs against the oracle, over one and several planning
+    chunks."""
+    from paper_1105_6040_amd import _native as N
+    lengths = many_segment_lengths(nseg, nlong, nseg + 7)
+    if nseg == 7:
+        lengths = np.array([8192, 1, 0, 300_000, 4097, 8193, 65_536], dtype=np.int64)
+    off = inputs.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    assert n > 8192 * nseg
+    say(f"work queue {dt} nseg={nseg} n={n}")
+    k = inputs.keys(dt, n, "uniform" if nseg != 1025 else "bits16", seed=nseg + 3)
+    v = np.arange(n, dtype=np.uint32)
+    old = N.tune_get(N.MS_TUNE_SEG_PASSES)
+    N.tune_set(N.MS_TUNE_SEG_PASSES, 2)
+    try:
+        assert np.array_equal(host(api.sort_segmented(dev(k), dev(off))), oracle.sort_segmented(k, off)), nseg
+        ko, vo = api.sort_segmented(dev(k), dev(off), dev(v))
+        ek, ev = oracle.sort_segmented(k, off, v)
+        assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), nseg
+    finally:
+        N.tune_set(N.MS_TUNE_SEG_PASSES, old)
+
+
 @pytest.mark.parametrize("nseg,nlong", [(1025, 60), (2049, 130)])
 def test_sort_segmented_one_launch_for_long_segments(nseg, nlong):
     """With MS_TUNE_SEG_PASSES = 0 segments averaging > 8,192 keys take the
@@ -600,12 +629,13 @@ def test_segments_workload_full_size():
     torch.cuda.synchronize()
     say(f"segments workload: all {lengths.size} segments against the oracle on {fullsize.THREADS} host threads")
     assert fullsize.compare_segments(k, out, off) == lengths.size
-    say("segments workload: the one-launch persistent kernel gives the same result")
     from paper_1105_6040_amd import _native as N
     old = N.tune_get(N.MS_TUNE_SEG_PASSES)
-    N.tune_set(N.MS_TUNE_SEG_PASSES, 0)
     try:
-        assert torch.equal(api.sort_segmented(k, toff), out)
+        for mode in (p for p in (0, 1, 2) if p != old):
+            say(f"segments workload: path MS_TUNE_SEG_PASSES={mode} gives the same result")
+            N.tune_set(N.MS_TUNE_SEG_PASSES, mode)
+            assert torch.equal(api.sort_segmented(k, toff), out), mode
     finally:
         N.tune_set(N.MS_TUNE_SEG_PASSES, old)
     del out, k
