@@ -44,10 +44,18 @@ def sources():
 RESOURCE_REMARKS = "-Rpass-analysis=kernel-resource-usage"
 
 
+# Kernels held to a register budget on purpose, with the spill each may
+# have (bytes per lane): the one-launch segment queue for 32-bit keys without
+# values runs two workgroups per CU at 128 registers with a small spill,
+# faster than one workgroup per CU without it.
+BOUNDED_SPILLS = {"segqueue_kernel_x2": 32}
+
+
 def spilling_kernels(remarks: str):
     """(kernel, bytes per lane) for every kernel whose resource-usage remark
     reports private scratch: register spills, which these kernels must not
-    have (a spilled tile kernel loses its occupancy and its speed)."""
+    have (a spilled tile kernel loses its occupancy and its speed), beyond
+    the bounded spills listed above."""
     out, name = [], None
     for ln in remarks.splitlines():
         m = re.search(r"Function Name: (\S+)", ln)
@@ -56,7 +64,10 @@ def spilling_kernels(remarks: str):
             continue
         m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", ln)
         if m and int(m.group(1)) > 0:
-            out.append((name, int(m.group(1))))
+            b = int(m.group(1))
+            if any(k in (name or "") and b <= lim for k, lim in BOUNDED_SPILLS.items()):
+                continue
+            out.append((name, b))
     return out
 
 

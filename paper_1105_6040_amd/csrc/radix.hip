@@ -587,10 +587,20 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
 // 16,384 keys (1,024 threads; a tunable).  The tile size is an argument of
 // the planning kernels and a template parameter of the pass.
 constexpr int kSegSweepThreads = 512;
-// Workspace words of the one-launch path's queue table and of one segment's
-// finished-tile counts (see segqueue_kernel).
-constexpr size_t kQWordsAll = 512;
-constexpr size_t kDoneWords = 32;
+// The one-launch path's queue table, a cleared block of the workspace of
+// kQWordsAll words: per queue, its ticket counter and its counts of finished
+// items per phase, each on a cache line of its own (every workgroup of an XCD
+// counts there); then the queues' record starts (kMaxQueues + 1 of them, the
+// last one the record count) and owners (XCC_ID + 1, 0 = unclaimed).
+constexpr int kMaxQueues = 8;
+constexpr int kLineWords = 32;
+constexpr int kQTickets = 0;
+constexpr int kQDone = kMaxQueues * kLineWords;
+constexpr int kQStarts = 2 * kMaxQueues * kLineWords;
+constexpr int kQOwners = kQStarts + kMaxQueues + 1;
+constexpr int kQWords = kQOwners + kMaxQueues;
+constexpr size_t kQWordsAll = 1024;
+static_assert(kQWords <= static_cast<int>(kQWordsAll), "queue table fits its block");
 // Used when the segments average more keys than one workgroup sorts in LDS
 // (8,192): shorter ones are sorted faster by one workgroup each.
 constexpr uint64_t kSegSweepMinAverage = 8192;
@@ -695,13 +705,36 @@ __device__ void write_segsweep_plan(SortPlan* plan, const Buffers& buf) {
   plan->num_active = P;
 }
 
+// The one-launch path splits the tile table (segment order) into kMaxQueues
+// contiguous queues of about equal tile counts, at segment boundaries: queue
+// q starts at the first segment whose first tile is at or after
+// ceil(q * total / kMaxQueues); a queue no segment starts in is empty.
+// Every start defaults to the tile count (queue 0's to 0) ...
+__device__ __forceinline__ void queue_start_defaults(uint32_t* qtab, uint32_t total) {
+  qtab[kQStarts] = 0;
+  for (int q = 1; q <= kMaxQueues; ++q) qtab[kQStarts + q] = total;
+}
+
+// ... and the one segment that crosses each boundary writes that queue's
+// start: the segment starting at tile g whose predecessor starts at tile
+// prev (prev_known false for segment 0).
+__device__ __forceinline__ void mark_queue_starts(uint32_t* qtab, uint32_t total, uint64_t g, uint64_t prev,
+                                                  bool prev_known) {
+  for (int q = 1; q < kMaxQueues; ++q) {
+    const uint64_t b = (static_cast<uint64_t>(q) * total + kMaxQueues - 1) / kMaxQueues;
+    if ((!prev_known || prev < b) && b <= g) qtab[kQStarts + q] = static_cast<uint32_t>(g < total ? g : total);
+  }
+}
+
 // Plan step 2 (one block): chunk starts by an exclusive scan of their tile
-// counts, the tile count, and the pass plan.
+// counts, the tile count, and the pass plan (and, given qtab, the queue
+// starts' defaults).
 template <typename K, bool VALS>
 __global__ __launch_bounds__(kSegPlanThreads) void segsweep_plan_kernel(uint64_t* __restrict__ chunk_start,
                                                                        uint32_t chunks, uint32_t max_tiles,
                                                                        uint32_t* __restrict__ num_tiles,
-                                                                       SortPlan* plan, Buffers buf) {
+                                                                       SortPlan* plan, Buffers buf,
+                                                                       uint32_t* __restrict__ qtab) {
   __shared__ uint64_t s_scan[kRadix / kWave];
   const int tid = threadIdx.x;
   uint64_t carry = 0;  // the same in every thread
@@ -718,6 +751,7 @@ __global__ __launch_bounds__(kSegPlanThreads) void segsweep_plan_kernel(uint64_t
   // the record and status tables); overlapping ones may give more, which
   // are dropped.
   *num_tiles = static_cast<uint32_t>(carry < max_tiles ? carry : max_tiles);
+  if (qtab) queue_start_defaults(qtab, *num_tiles);
   write_segsweep_plan<K, VALS>(plan, buf);
 }
 
@@ -726,9 +760,12 @@ __global__ __launch_bounds__(kSegPlanThreads) void segsweep_plan_kernel(uint64_t
 // its segment by a binary search over the chunk's segment starts in LDS).
 // Records from max_tiles on are not written: the local starts are held
 // saturated at the room left below max_tiles.  Returns the chunk's tile
-// count.
+// count.  Given qtab, also marks the queue starts that fall in the chunk
+// (num_tiles: the tile count from plan step 2, or nullptr when this block
+// holds every segment and sets the defaults itself).
 __device__ uint64_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, uint64_t n, uint32_t tile,
-                               uint64_t base, uint32_t max_tiles, uint32_t* wide, SegTile* __restrict__ tiles) {
+                               uint64_t base, uint32_t max_tiles, uint32_t* wide, SegTile* __restrict__ tiles,
+                               uint32_t* qtab, const uint32_t* num_tiles) {
   __shared__ uint64_t s_scan[kRadix / kWave];
   __shared__ uint32_t s_start[kSegChunk + 1];  // tile start of each segment of the chunk, block-relative
   __shared__ uint64_t s_off[kSegChunk + 1];    // the chunk's offsets, clamped to n
@@ -737,6 +774,16 @@ __device__ uint64_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, 
   const uint32_t room = static_cast<uint32_t>(base < max_tiles ? max_tiles - base : 0u);
   uint64_t total;
   const uint64_t start = chunk_tiles(off, nseg, n, tile, wide, s_scan, &total);
+  uint32_t all = 0;  // the capped tile count, for the queue starts
+  if (qtab) {
+    if (num_tiles) {
+      all = *num_tiles;
+    } else {
+      all = static_cast<uint32_t>(total < max_tiles ? total : max_tiles);
+      if (threadIdx.x == 0) queue_start_defaults(qtab, all);
+      __syncthreads();
+    }
+  }
   {
     const uint32_t l0 = threadIdx.x * kSegPlanPerThread;
     uint64_t run = start;
@@ -744,7 +791,14 @@ __device__ uint64_t fill_chunk(const uint64_t* __restrict__ off, uint32_t nseg, 
     for (int i = 0; i < kSegPlanPerThread; ++i)
       if (l0 + i < nloc) {
         s_start[l0 + i] = static_cast<uint32_t>(run < room ? run : room);
-        run += segment_tiles(off, first_seg + l0 + i, n, tile);
+        const uint32_t sg = first_seg + l0 + i;
+        const uint64_t len = segment_tiles(off, sg, n, tile);
+        if (qtab) {
+          const uint64_t g = base + run;
+          const uint64_t prev = sg == 0 ? 0 : g - segment_tiles(off, sg - 1, n, tile);
+          mark_queue_starts(qtab, all, g, prev, sg != 0);
+        }
+        run += len;
       }
     if (threadIdx.x == 0) s_start[nloc] = static_cast<uint32_t>(total < room ? total : room);
     for (uint32_t i = threadIdx.x; i <= nloc; i += kSegPlanThreads) {
@@ -785,8 +839,10 @@ __global__ __launch_bounds__(kSegPlanThreads) void segsweep_fill_kernel(const ui
                                                                        uint32_t nseg, uint64_t n, uint32_t tile,
                                                                        const uint64_t* __restrict__ chunk_start,
                                                                        uint32_t max_tiles, uint32_t* wide,
-                                                                       SegTile* __restrict__ tiles) {
-  fill_chunk(off, nseg, n, tile, chunk_start[blockIdx.x], max_tiles, wide, tiles);
+                                                                       SegTile* __restrict__ tiles,
+                                                                       uint32_t* __restrict__ qtab,
+                                                                       const uint32_t* __restrict__ num_tiles) {
+  fill_chunk(off, nseg, n, tile, chunk_start[blockIdx.x], max_tiles, wide, tiles, qtab, num_tiles);
 }
 
 // The whole plan in one launch when the segments form one chunk (at most
@@ -797,8 +853,8 @@ __global__ __launch_bounds__(kSegPlanThreads) void segsweep_plan1_kernel(const u
                                                                         uint32_t max_tiles, uint32_t* wide,
                                                                         uint32_t* __restrict__ num_tiles,
                                                                         SegTile* __restrict__ tiles, SortPlan* plan,
-                                                                        Buffers buf) {
-  const uint64_t total = fill_chunk(off, nseg, n, tile, 0u, max_tiles, wide, tiles);
+                                                                        Buffers buf, uint32_t* __restrict__ qtab) {
+  const uint64_t total = fill_chunk(off, nseg, n, tile, 0u, max_tiles, wide, tiles, qtab, nullptr);
   if (threadIdx.x != 0) return;
   *num_tiles = static_cast<uint32_t>(total < max_tiles ? total : max_tiles);
   write_segsweep_plan<K, VALS>(plan, buf);
@@ -1030,53 +1086,39 @@ __global__ __launch_bounds__(THREADS) void segsweep_pass_kernel(
 
 // ---------------------------------------------------------------------------
 // 6. The same segment passes as ONE persistent launch: a work queue of
-// (phase, tile) items over a tile table like the one above.  Phase 0 of a
-// segment of several tiles counts its keys for the P digit histograms; phase
-// 1 + p is digit pass p over its tiles (decoupled look-back inside the
-// segment, bases from the segment's histogram).  A segment of one tile is
-// sorted whole in LDS in phase 0 and takes no later phase.
+// (phase, tile) items over the tile table above.  Phase 0 of a segment of
+// several tiles counts its keys for the P digit histograms; phase 1 + p is
+// digit pass p over its tiles (decoupled look-back inside the segment, bases
+// from the segment's histogram).  A segment of one tile is sorted whole in
+// LDS in phase 0 and has nothing to do in the later phases.
 //
 // XCD-aware: the chip's L2 is one cache per XCD, and one XCD's L2 is not
 // kept coherent with another's inside a kernel.  Keys written in one phase
 // are read by other workgroups in the next, so every segment is given to one
-// XCD: segment s goes to queue s % Q, and each queue is claimed by the first
-// workgroup that finds it unclaimed, for the XCD that workgroup runs on (its
-// XCC_ID hardware register); only workgroups of the owning XCD take its
-// tickets.  A workgroup serves a queue its XCD owns while one has tickets
-// left, then claims an unclaimed one, and exits when neither remains, so
-// every queue is served whatever the number of XCDs.  Inside an XCD the L1s are
-// write-through into the shared L2, so a tile publishes a finished phase by
-// waiting for its own stores and counting itself done, and a tile that waited
-// invalidates its CU's L1 before reading -- no L2 write-back or invalidation,
-// which across XCDs would be needed for every tile.  Q is 8 (every XCD) for
-// large inputs and 1 (one XCD, whose L2 then holds the whole working set) for
-// small ones.  Look-back status words and the per-segment histograms are read
-// and written with device-coherent atomics, as in the other passes.
+// XCD: the table is cut into kMaxQueues queues of consecutive segments with
+// about equal tile counts, and each queue is served by one XCD -- queue x by
+// the XCD whose XCC_ID is x, claimed for it by the first of its workgroups.
+// A workgroup whose queue has no tickets left claims an unclaimed queue that
+// still has some (so that every queue is served on a device with fewer
+// XCDs), and exits when there is none.
 //
 // Tickets of a queue run phase-major (every tile's phase 0, then every tile's
-// phase 1, ...), so an item only waits for items with earlier tickets of its
-// own queue -- the previous phase of its own segment (a per-segment count of
-// finished tiles) and, inside a pass, the look-back -- which are already
-// running: no wait can deadlock.  Look-back rows: two buffers, pass p in
-// buffer p % 2; phase 0 clears a tile's row in both, and pass p (p >= 1)
-// clears the tile's row of buffer (p + 1) % 2 for pass p + 1, after pass
-// p - 1 of the segment -- the last reader of that row -- is done.
-constexpr int kMaxQueues = 8;
-// The queue table (its own cleared block of the workspace): each queue's
-// ticket counter on a cache line of its own (every workgroup of an XCD takes
-// tickets there), then the queues' record starts, record counts and owners
-// (XCC_ID + 1, 0 = unclaimed).  A segment's finished-tile counts likewise
-// take a cache line per segment: tiles waiting on one segment poll it while
-// tiles of neighbouring segments count themselves done.
-constexpr int kLineWords = 32;
-constexpr int kQTickets = 0;
-constexpr int kQStarts = kMaxQueues * kLineWords;
-constexpr int kQTotals = kQStarts + kMaxQueues;
-constexpr int kQOwners = kQTotals + kMaxQueues;
-constexpr int kQWords = kQOwners + kMaxQueues;
-constexpr int kDoneStride = kLineWords;
-static_assert(kDoneStride >= kMaxPasses + 1 && kDoneStride == kDoneWords, "one line of phase counts per segment");
-static_assert(kQWords <= static_cast<int>(kQWordsAll), "queue table fits its block");
+// phase 1, ...), and an item of phase f > 0 waits until every item of phase
+// f - 1 of its queue has counted itself done (a count per phase and queue).
+// An item only waits for items with earlier tickets of its own queue -- that
+// count and, inside a pass, the look-back -- so no wait can deadlock, even
+// with a workgroup holding its next ticket while it runs the current item
+// (tickets run one item ahead).  A finishing item waits for its own stores
+// before it counts itself done; a workgroup that sees a phase complete
+// invalidates its CU's L1 and its XCD's non-coherent L2 lines before reading
+// the keys of the next phase (once per phase and workgroup).  Look-back
+// status words and the per-segment histograms are read and written with
+// device-coherent atomics, as in the other passes.
+//
+// Look-back rows: two buffers, pass p in buffer p % 2; phase 0 clears a
+// tile's row in both, and pass p (p >= 1) clears the tile's row of buffer
+// (p + 1) % 2 for pass p + 1, once pass p - 1 -- the last reader of that
+// row -- is complete.
 
 __device__ __forceinline__ uint32_t xcc_id() {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -1088,157 +1130,81 @@ __device__ __forceinline__ uint32_t xcc_id() {
 #endif
 }
 
-// Invalidates this CU's vector L1, so that the following loads read what
-// other CUs of the same XCD have written into the shared L2.
-__device__ __forceinline__ void invalidate_l1() {
+// Invalidates this CU's vector L1 and the non-coherent lines of its XCD's L2
+// (the acquire side of device scope), so that the following loads read what
+// other CUs have written.  Measured: the L1 invalidation alone still let
+// stale keys through to the next phase now and then.
+__device__ __forceinline__ void invalidate_caches() {
 #if defined(__HIP_DEVICE_COMPILE__)
-  asm volatile("buffer_inv sc0" ::: "memory");
+  asm volatile("buffer_inv sc1" ::: "memory");
 #endif
 }
 
-// Tiles of this block's segments for each of the nq queues (segment s in
-// queue s % nq; a thread's kSegPlanPerThread = 8 segments fall in queues
-// i % nq); per queue, the thread's exclusive start in the block and the
-// block's total.
-__device__ __forceinline__ void chunk_queue_tiles(const uint64_t* off, uint32_t nseg, uint64_t n, uint32_t tile,
-                                                  uint32_t nq, uint64_t* s_scan, uint64_t (&start)[kMaxQueues],
-                                                  uint64_t (&total)[kMaxQueues], uint64_t (&mine)[kMaxQueues]) {
-  static_assert(kSegPlanPerThread == kMaxQueues, "one segment of each queue per thread");
-  const uint32_t s0 = blockIdx.x * kSegChunk + threadIdx.x * kSegPlanPerThread;
-#pragma unroll
-  for (int q = 0; q < kMaxQueues; ++q) mine[q] = 0;
-#pragma unroll
-  for (int i = 0; i < kSegPlanPerThread; ++i)
-    if (s0 + i < nseg) {
-      uint64_t b;
-      const uint64_t len = segment_span(off, s0 + i, n, &b);
-      mine[i % nq] += (len + tile - 1) / tile;
-    }
-  for (uint32_t q = 0; q < nq; ++q) {
-    start[q] = block_exclusive_scan_radix<kSegPlanThreads>(mine[q], s_scan, &total[q]);
-    __syncthreads();
-  }
-}
-
-// Plan step 1: per (chunk, queue) tile counts, row c of `counts`.
-__global__ __launch_bounds__(kSegPlanThreads) void segq_count_kernel(const uint64_t* __restrict__ off, uint32_t nseg,
-                                                                    uint64_t n, uint32_t tile, uint32_t nq,
-                                                                    uint64_t* __restrict__ counts) {
-  __shared__ uint64_t s_scan[kRadix / kWave];
-  uint64_t start[kMaxQueues], total[kMaxQueues], mine[kMaxQueues];
-  chunk_queue_tiles(off, nseg, n, tile, nq, s_scan, start, total, mine);
-  if (threadIdx.x < nq) {
-    uint64_t t = 0;
-#pragma unroll
-    for (int q = 0; q < kMaxQueues; ++q)
-      if (q == static_cast<int>(threadIdx.x)) t = total[q];
-    counts[static_cast<size_t>(blockIdx.x) * kMaxQueues + threadIdx.x] = t;
-  }
-}
-
-// Plan step 2 (one block): record starts of every (chunk, queue), queue-major
-// (queue 0's tiles of every chunk, then queue 1's, ...), in place of the
-// counts; the queue table (start and record count of every queue, the table
-// capped at max_tiles) and the pass plan.
-template <typename K, bool VALS>
-__global__ __launch_bounds__(kSegPlanThreads) void segq_plan_kernel(uint64_t* __restrict__ counts, uint32_t chunks,
-                                                                   uint32_t nq, uint32_t max_tiles,
-                                                                   uint32_t* __restrict__ ctrs,
-                                                                   uint32_t* __restrict__ qtab, SortPlan* plan,
-                                                                   Buffers buf) {
-  __shared__ uint64_t s_scan[kRadix / kWave];
-  const int tid = threadIdx.x;
-  uint64_t carry = 0;
-  for (uint32_t q = 0; q < nq; ++q) {
-    if (tid == 0) qtab[kQStarts + q] = static_cast<uint32_t>(carry < max_tiles ? carry : max_tiles);
-    for (uint32_t c0 = 0; c0 < chunks; c0 += kSegPlanThreads) {
-      const uint32_t c = c0 + tid;
-      const uint64_t v = c < chunks ? counts[static_cast<size_t>(c) * kMaxQueues + q] : 0u;
-      uint64_t sum;
-      const uint64_t ex = block_exclusive_scan_radix<kSegPlanThreads>(v, s_scan, &sum);
-      if (c < chunks) counts[static_cast<size_t>(c) * kMaxQueues + q] = carry + ex;
-      carry += sum;
-      __syncthreads();
-    }
-  }
-  if (tid != 0) return;
-  const uint32_t table = static_cast<uint32_t>(carry < max_tiles ? carry : max_tiles);
-  ctrs[0] = table;
-  for (uint32_t q = 0; q < nq; ++q) {
-    const uint32_t b = qtab[kQStarts + q];
-    const uint32_t e = q + 1 < nq ? qtab[kQStarts + q + 1] : table;
-    qtab[kQTotals + q] = e - b;
-  }
-  write_segsweep_plan<K, VALS>(plan, buf);
-}
-
-// Plan step 3: this chunk's records, queue by queue, at the starts step 2
-// wrote; records at max_tiles and beyond are not written.
-__global__ __launch_bounds__(kSegPlanThreads) void segq_fill_kernel(const uint64_t* __restrict__ off, uint32_t nseg,
-                                                                   uint64_t n, uint32_t tile, uint32_t nq,
-                                                                   const uint64_t* __restrict__ starts,
-                                                                   uint32_t max_tiles, SegTile* __restrict__ tiles) {
-  __shared__ uint64_t s_scan[kRadix / kWave];
-  __shared__ uint64_t s_start[kSegPlanThreads + 1];  // per thread: first local tile of its segment of queue q
-  uint64_t start[kMaxQueues], total[kMaxQueues], mine[kMaxQueues];
-  chunk_queue_tiles(off, nseg, n, tile, nq, s_scan, start, total, mine);
-  const uint32_t s0 = blockIdx.x * kSegChunk + threadIdx.x * kSegPlanPerThread;
-  for (uint32_t q = 0; q < nq; ++q) {
-    uint64_t my_start = 0, tot = 0;
-#pragma unroll
-    for (int k = 0; k < kMaxQueues; ++k)
-      if (k == static_cast<int>(q)) {
-        my_start = start[k];
-        tot = total[k];
+// The claim of a ticket by thread 0: from queue q while it has tickets left
+// (t_first: a ticket of q already taken, or ~0u to take one here), else from
+// this XCD's own queue (number XCC_ID, claimed for the XCD by whichever of its
+// workgroups comes first), else from another queue this XCD owns with tickets
+// left, else from a queue claimed now for this XCD.  Returns the queue (-1:
+// none is left) and the ticket in *t.  With as many queues as XCDs every XCD
+// serves its own; the other claims keep every queue served on a device with
+// fewer XCDs (or other XCC_IDs).
+template <int P>
+__device__ int claim_ticket(uint32_t* qtab, uint32_t nq, uint32_t me, int q, uint32_t t_first, uint32_t* t) {
+  uint32_t* const owner = qtab + kQOwners;
+  auto total = [&](uint32_t k) { return (P + 1) * (qtab[kQStarts + k + 1] - qtab[kQStarts + k]); };
+  auto left = [&](uint32_t k) {
+    return __hip_atomic_load(&qtab[kQTickets + k * kLineWords], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           total(k);
+  };
+  auto owner_of = [&](uint32_t k) { return __hip_atomic_load(&owner[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+  bool have = t_first != ~0u;
+  while (true) {
+    if (q >= 0) {
+      const uint32_t tot = total(q);
+      const uint32_t v = have ? t_first : atomicAdd(&qtab[kQTickets + q * kLineWords], 1u);
+      have = false;
+      if (v < tot) {
+        *t = v;
+        return q;
       }
-    s_start[threadIdx.x] = my_start;
-    if (threadIdx.x == 0) s_start[kSegPlanThreads] = tot;
-    __syncthreads();
-    const uint64_t base = starts[static_cast<size_t>(blockIdx.x) * kMaxQueues + q];
-    for (uint64_t t = threadIdx.x; t < tot; t += kSegPlanThreads) {
-      if (base + t >= max_tiles) break;
-      // The thread whose queue-q segments hold local tile t: the last one
-      // whose start is <= t (its segment then has a tile at t).
-      uint32_t lo = 0, hi = kSegPlanThreads;
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) / 2;
-        if (s_start[mid] <= t)
-          lo = mid;
-        else
-          hi = mid;
+      q = -1;
+    }
+    const uint32_t x = me - 1;
+    if (x < nq) {
+      uint32_t v = owner_of(x);
+      if (v == 0) {
+        v = atomicCAS(&owner[x], 0u, me);
+        if (v == 0) v = me;
       }
-      // Thread lo's segments of queue q: i = q, q + nq, ... < 8, in order.
-      uint64_t run = s_start[lo];
-      for (uint32_t i = q; i < static_cast<uint32_t>(kSegPlanPerThread); i += nq) {
-        const uint32_t sg = blockIdx.x * kSegChunk + lo * kSegPlanPerThread + i;
-        if (sg >= nseg) break;
-        uint64_t b;
-        const uint64_t len = segment_span(off, sg, n, &b);
-        const uint64_t nt = (len + tile - 1) / tile;
-        if (t < run + nt) {
-          const uint64_t j = t - run;
-          const uint64_t tb = b + j * tile;
-          SegTile r;
-          r.begin = tb;
-          r.count = static_cast<uint32_t>(len - j * tile < tile ? len - j * tile : tile) | (j == 0 ? kTileFirst : 0u) |
-                    (nt == 1 ? kTileOnly : 0u);
-          r.seg = sg;
-          tiles[base + t] = r;
-          break;
-        }
-        run += nt;
+      if (v == me && left(x)) {
+        q = static_cast<int>(x);
+        continue;
       }
     }
-    __syncthreads();
+    for (uint32_t k = 0; k < nq && q < 0; ++k)
+      if (owner_of(k) == me && left(k)) q = static_cast<int>(k);
+    if (q >= 0) continue;
+    // No queue of this XCD has tickets left: claim the first unclaimed one.
+    // A lost race means another workgroup -- perhaps of this XCD -- just
+    // claimed it: look at the owned queues again before claiming another.
+    // Owners only ever change from 0, so this ends after at most nq lost
+    // races.
+    bool unclaimed = false;
+    for (uint32_t k = 0; k < nq; ++k) {
+      if (owner_of(k) != 0 || !left(k)) continue;
+      unclaimed = true;
+      if (atomicCAS(&owner[k], 0u, me) == 0u) q = static_cast<int>(k);
+      break;
+    }
+    if (!unclaimed) return -1;
   }
-  (void)s0;
 }
 
 template <typename K, bool VALS, typename C, typename S>
-__global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
-    const SortPlan* __restrict__ plan, const SegTile* __restrict__ tiles, const uint32_t* __restrict__ ctrs,
-    uint32_t* __restrict__ qtab, uint32_t nq, const uint64_t* __restrict__ off, uint64_t n, K flip,
-    C* __restrict__ seg_hist, uint32_t* __restrict__ done, S* status0, S* status1) {
+__device__ __forceinline__ void segqueue_body(const SortPlan* __restrict__ plan, const SegTile* __restrict__ tiles,
+                                              uint32_t* __restrict__ qtab, const uint64_t* __restrict__ off,
+                                              uint64_t n, K flip, C* __restrict__ seg_hist, S* status0, S* status1) {
+  constexpr uint32_t nq = kMaxQueues;
   constexpr int kThreads = kSegSweepThreads;
   constexpr int kKpt = PassCfg<kThreads>::kKpt;
   constexpr int kTile = PassCfg<kThreads>::kTile;
@@ -1258,66 +1224,53 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
   __shared__ uint32_t s_scan[kThreads / kWave];
   __shared__ C s_cscan[kRadix / kWave];
   __shared__ C s_cscan2[kRadix / kWave];
+  __shared__ int s_q;
   __shared__ uint32_t s_ticket;
 
   const int tid = threadIdx.x;
   const uint32_t me = xcc_id() + 1;
-  uint32_t* const owner = qtab + kQOwners;
-  const uint32_t table = ctrs[0];
-  __shared__ int s_q;
-  int q = -1;  // the queue this workgroup serves (uniform)
 
-  while (true) {
-    if (tid == 0) {
-      // The next ticket: from the current queue, else from another queue this
-      // XCD owns that has tickets left, else from a queue this workgroup
-      // claims for its XCD; none: done.
-      uint32_t t = 0;
-      while (true) {
-        if (q >= 0) {
-          const uint32_t tot = (P + 1) * qtab[kQTotals + q];
-          t = atomicAdd(&qtab[kQTickets + q * kLineWords], 1u);
-          if (t < tot) break;
-          q = -1;
-        }
-        for (uint32_t k = 0; k < nq && q < 0; ++k) {
-          const uint32_t tot = (P + 1) * qtab[kQTotals + k];
-          if (__hip_atomic_load(&owner[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == me &&
-              __hip_atomic_load(&qtab[kQTickets + k * kLineWords], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tot)
-            q = static_cast<int>(k);
-        }
-        for (uint32_t k = 0; k < nq && q < 0; ++k)
-          if (__hip_atomic_load(&owner[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-              atomicCAS(&owner[k], 0u, me) == 0u)
-            q = static_cast<int>(k);
-        if (q < 0) break;
-      }
-      s_q = q;
-      s_ticket = t;
-    }
-    __syncthreads();
-    q = s_q;
-    if (q < 0) break;
-    const uint32_t T = qtab[kQTotals + q];
-    const uint64_t ticket = s_ticket;
-    const uint32_t phase = static_cast<uint32_t>(ticket / T);
-    const uint32_t i = qtab[kQStarts + q] + static_cast<uint32_t>(ticket % T);
+  // The first ticket.
+  if (tid == 0) {
+    uint32_t t = 0;
+    s_q = claim_ticket<P>(qtab, nq, me, -1, ~0u, &t);
+    s_ticket = t;
+  }
+  __syncthreads();
+  // The current item's queue and ticket, uniform: kept in scalar registers.
+  int q = __builtin_amdgcn_readfirstlane(s_q);
+  uint32_t ticket = __builtin_amdgcn_readfirstlane(s_ticket);
+  int known = -1;              // phases of queue q known to be complete: 0 .. known
+  bool loaded = false;         // the current item's keys are already in `keys`
+  K keys[kKpt];
+  uint32_t vals[kKpt];
+
+  while (q >= 0) {
+    const uint32_t T = qtab[kQStarts + q + 1] - qtab[kQStarts + q];
+    const uint32_t phase = ticket / T;
+    const uint32_t i = qtab[kQStarts + q] + ticket % T;
+    uint32_t* const qdone = qtab + kQDone + q * kLineWords;
     const SegTile r = tiles[i];
     const uint32_t cnt = r.count & kTileCountMask;
     const uint64_t tbeg = r.begin;
     const uint64_t tend = tbeg + cnt;
     const bool only = (r.count & kTileOnly) != 0;
     const bool first = (r.count & kTileFirst) != 0;
+    const uint32_t seg = r.seg;
+    C* const h = seg_hist + static_cast<size_t>(seg) * P * kRadix;
 
-    if (only) {
-      if (phase == 0) {
+    // The next ticket of this queue, taken now and resolved later: tickets
+    // run one item ahead.
+    uint32_t raw_next = 0;
+    if (tid == 0) raw_next = atomicAdd(&qtab[kQTickets + q * kLineWords], 1u);
+
+    if (only || phase == 0) {
+      if (only && phase == 0) {
         // The whole segment in one tile: every digit pass in LDS, in place.
         const K* src = static_cast<const K*>(plan->pass[0].src_k);
         const uint32_t* srcv = plan->pass[0].src_v;
         K* dst = static_cast<K*>(plan->pass[P - 1].dst_k);
         uint32_t* dstv = plan->pass[P - 1].dst_v;
-        K keys[kKpt];
-        uint32_t vals[kKpt];
         load_tile_keys<K, VALS, uint64_t, kKpt>(as_global(src), as_global(srcv),
                                                 tbeg + static_cast<uint64_t>(tid) * kKpt, tend, ~K(0) ^ flip, keys,
                                                 vals);
@@ -1330,71 +1283,78 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
           dst[tbeg + e] = s_stage[pad16(e)] ^ flip;
           if constexpr (VALS) dstv[tbeg + e] = s_vstage[pad16(e)];
         }
+      } else if (!only) {
+        // Phase 0: the tile's counts of every digit added to its segment's
+        // histograms; its look-back rows cleared in both buffers.
+        for (int e = tid; e < kRadix; e += kThreads) {
+          status_store(&status0[static_cast<size_t>(i) * kRadix + e], S(0));
+          status_store(&status1[static_cast<size_t>(i) * kRadix + e], S(0));
+        }
+        for (int e = tid; e < P * kRadix; e += kThreads) s_h[e] = 0;
+        __syncthreads();
+        uint32_t unused[kKpt];
+        load_tile_keys<K, false, uint64_t, kKpt>(as_global(static_cast<const K*>(plan->pass[0].src_k)),
+                                                 gptr<const uint32_t>(nullptr),
+                                                 tbeg + static_cast<uint64_t>(tid) * kKpt, tend, K(0), keys, unused);
+#pragma unroll
+        for (int k = 0; k < kKpt; ++k) {
+          if (static_cast<uint32_t>(tid * kKpt + k) < cnt) {
+            const K key = flip_key(keys[k], flip);
+#pragma unroll
+            for (int p = 0; p < P; ++p) atomicAdd(&s_h[p * kRadix + digit_of(key, 8 * p)], 1u);
+          }
+        }
+        __syncthreads();
+        for (int e = tid; e < P * kRadix; e += kThreads)
+          if (s_h[e]) atomic_add_c(&h[e], static_cast<C>(s_h[e]));
+      }
+      // Every wave's stores and atomics complete before the item counts
+      // itself done (a one-tile segment's later phases have nothing to do).
+      __builtin_amdgcn_s_waitcnt(waitcnt_vmcnt(0));
+      __syncthreads();
+      if (tid == 0) {
+        __hip_atomic_fetch_add(&qdone[phase], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t t = 0;
+        const int nq2 = claim_ticket<P>(qtab, nq, me, q, raw_next, &t);
+        s_q = nq2;
+        s_ticket = t;
       }
       __syncthreads();
+      const int q2 = __builtin_amdgcn_readfirstlane(s_q);
+      if (q2 != q) known = -1;
+      q = q2;
+      ticket = __builtin_amdgcn_readfirstlane(s_ticket);
+      loaded = false;
+      __syncthreads();  // s_q and s_ticket are written again by the next item
       continue;
     }
 
-    // A tile of a segment of several tiles.  Its records are consecutive
-    // from index i - j (j = this tile's place in the segment); a table capped
-    // by offsets that break the contract may hold only the first ones, and a
-    // phase is complete when every record present has finished it.
-    const uint32_t seg = r.seg;
-    uint64_t sb;
-    const uint64_t slen = segment_span(off, seg, n, &sb);
-    const uint32_t j = static_cast<uint32_t>((tbeg - sb) / kTile);
-    const uint64_t seg_tiles = (slen + kTile - 1) / kTile;
-    const uint32_t present = static_cast<uint32_t>(std::min<uint64_t>(seg_tiles, table - (i - j)));
-    uint32_t* const d = done + static_cast<size_t>(seg) * kDoneStride;
-    C* const h = seg_hist + static_cast<size_t>(seg) * P * kRadix;
-
-    if (phase == 0) {
-      for (int e = tid; e < kRadix; e += kThreads) {
-        status_store(&status0[static_cast<size_t>(i) * kRadix + e], S(0));
-        status_store(&status1[static_cast<size_t>(i) * kRadix + e], S(0));
-      }
-      for (int e = tid; e < P * kRadix; e += kThreads) s_h[e] = 0;
-      __syncthreads();
-      K keys[kKpt];
-      uint32_t unused[kKpt];
-      load_tile_keys<K, false, uint64_t, kKpt>(as_global(static_cast<const K*>(plan->pass[0].src_k)),
-                                               gptr<const uint32_t>(nullptr),
-                                               tbeg + static_cast<uint64_t>(tid) * kKpt, tend, K(0), keys, unused);
-#pragma unroll
-      for (int k = 0; k < kKpt; ++k) {
-        if (static_cast<uint32_t>(tid * kKpt + k) < cnt) {
-          const K key = flip_key(keys[k], flip);
-#pragma unroll
-          for (int p = 0; p < P; ++p) atomicAdd(&s_h[p * kRadix + digit_of(key, 8 * p)], 1u);
+    // Digit pass p of a tile of a segment of several tiles, once phase p - 1
+    // (and so every earlier phase) of the whole queue is complete.
+    const int p = static_cast<int>(phase) - 1;
+    if (known < static_cast<int>(phase) - 1) {
+      if (tid == 0) {
+        // Back off while waiting: every poll is a device-coherent read of the
+        // line that finishing items count themselves done on.
+        int nap = 1;
+        while (__hip_atomic_load(&qdone[phase - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < T) {
+          for (int k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(8);
+          nap = nap < 16 ? 2 * nap : 16;
         }
       }
       __syncthreads();
-      for (int e = tid; e < P * kRadix; e += kThreads)
-        if (s_h[e]) atomic_add_c(&h[e], static_cast<C>(s_h[e]));
-      // Every wave's atomics and stores complete before the tile counts
-      // itself done.
-      __builtin_amdgcn_s_waitcnt(waitcnt_vmcnt(0));
-      __syncthreads();
-      if (tid == 0) __hip_atomic_fetch_add(&d[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      continue;
+      invalidate_caches();  // the previous phase's keys, written by other CUs
+      known = static_cast<int>(phase) - 1;
     }
-
-    // Digit pass p, once the segment's previous phase is complete.
-    const int p = static_cast<int>(phase) - 1;
-    if (tid == 0) {
-      // Back off while waiting: every poll is a device-coherent read of the
-      // line that finishing tiles count themselves done on.
-      int nap = 1;
-      while (__hip_atomic_load(&d[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < present) {
-        for (int k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(8);
-        nap = nap < 16 ? 2 * nap : 16;
-      }
-    }
-    __syncthreads();
-    invalidate_l1();  // the previous phase's keys, written by other CUs of this XCD
+    uint64_t sb;
+    (void)segment_span(off, seg, n, &sb);
+    const C hc = tid < kRadix
+                     ? __hip_atomic_load(&h[p * kRadix + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : C(0);
 
     S* const cur = (p & 1) ? status1 : status0;
     if (p >= 1) {
+      // The row's last reader, pass p - 1 of this queue, is complete.
       S* const later = (p & 1) ? status0 : status1;
       for (int e = tid; e < kRadix; e += kThreads) status_store(&later[static_cast<size_t>(i) * kRadix + e], S(0));
     }
@@ -1408,10 +1368,9 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
     const K out_flip = pp.last ? flip : K(0);
     const K pad = ~K(0) ^ in_flip;
 
-    K keys[kKpt];
-    uint32_t vals[kKpt];
-    load_tile_keys<K, VALS, uint64_t, kKpt>(src, src_v, tbeg + static_cast<uint64_t>(tid) * kKpt, tend, pad, keys,
-                                            vals);
+    if (!loaded)
+      load_tile_keys<K, VALS, C, kKpt>(src, src_v, static_cast<C>(tbeg) + static_cast<C>(tid) * kKpt,
+                                       static_cast<C>(tend), pad, keys, vals);
 #pragma unroll
     for (int k = 0; k < kKpt; ++k) keys[k] = flip_key(keys[k], in_flip);
     for (int e = tid; e < kRadix; e += kThreads) s_hist[e] = 0;
@@ -1427,15 +1386,35 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
       status_store(st, (first ? St::kInc : St::kAgg) | static_cast<S>(tcnt));
     }
     tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift, s_stage, s_vstage, s_counts, s_scan, true);
+    // The next item, known by now unless this queue ran out of tickets.
+    if (tid == 0) {
+      uint32_t t = 0;
+      s_q = claim_ticket<P>(qtab, nq, me, q, raw_next, &t);
+      s_ticket = t;
+    }
     S pred = 0;
     if (tid < kRadix && !first) pred = status_load(st - kRadix);
     tile_split_stage<kThreads, kKpt, VALS>(keys, vals, shift + kSubBits, s_stage, s_vstage, s_counts, s_scan, false);
     C tile_total, seg_total;
     const C start = block_exclusive_scan_radix<kThreads>(static_cast<C>(tcnt), s_cscan, &tile_total);
-    const C hc = tid < kRadix
-                     ? __hip_atomic_load(&h[p * kRadix + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                     : C(0);
     const C base = block_exclusive_scan_radix<kThreads>(hc, s_cscan2, &seg_total);
+
+    // The next item's keys load into the registers during the look-back and
+    // the scatter when it is a tile of this same pass (of a segment of
+    // several tiles): its dependency is then already met.
+    const int nq2 = __builtin_amdgcn_readfirstlane(s_q);
+    const uint32_t nticket = __builtin_amdgcn_readfirstlane(s_ticket);
+    bool next_loaded = false;
+    if (nq2 == q && nticket / T == phase) {
+      const SegTile nr = tiles[qtab[kQStarts + q] + nticket % T];
+      if ((nr.count & kTileOnly) == 0) {
+        const C nb = static_cast<C>(nr.begin);
+        load_tile_keys<K, VALS, C, kKpt>(src, src_v, nb + static_cast<C>(tid) * kKpt,
+                                         nb + static_cast<C>(nr.count & kTileCountMask), pad, keys, vals);
+        next_loaded = true;
+      }
+    }
+
     if (tid < kRadix) {
       C excl = 0;
       if (!first) {
@@ -1449,15 +1428,37 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
 #pragma unroll 4
     for (int e = tid; e < static_cast<int>(cnt); e += kThreads) {
       const K k = s_stage[pad16(e)];
-      uint64_t o = static_cast<uint64_t>(s_doff[digit_of(k, shift)]) + static_cast<uint64_t>(e);
-      o = o < n ? o : n - 1;
+      C o = s_doff[digit_of(k, shift)] + static_cast<C>(e);
+      o = o < static_cast<C>(n) ? o : static_cast<C>(n) - 1;
       dst[o] = k ^ out_flip;
       if constexpr (VALS) dst_v[o] = s_vstage[pad16(e)];
     }
+    // Every wave's stores complete before the tile counts itself done.
     __builtin_amdgcn_s_waitcnt(waitcnt_vmcnt(0));
     __syncthreads();
-    if (tid == 0) __hip_atomic_fetch_add(&d[p + 1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) __hip_atomic_fetch_add(&qdone[phase], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (nq2 != q) known = -1;
+    q = nq2;
+    ticket = nticket;
+    loaded = next_loaded;
   }
+}
+
+template <typename K, bool VALS, typename C, typename S>
+__global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
+    const SortPlan* __restrict__ plan, const SegTile* __restrict__ tiles, uint32_t* __restrict__ qtab,
+    const uint64_t* __restrict__ off, uint64_t n, K flip, C* __restrict__ seg_hist, S* status0, S* status1) {
+  segqueue_body<K, VALS, C, S>(plan, tiles, qtab, off, n, flip, seg_hist, status0, status1);
+}
+
+// The same for 32-bit keys without values, held to 128 registers so that two
+// workgroups share a CU (a few registers spill; with values or 64-bit keys
+// the spills would cost more than the second workgroup gains).
+template <typename K, bool VALS, typename C, typename S>
+__global__ __launch_bounds__(kSegSweepThreads) __attribute__((amdgpu_waves_per_eu(4))) void segqueue_kernel_x2(
+    const SortPlan* __restrict__ plan, const SegTile* __restrict__ tiles, uint32_t* __restrict__ qtab,
+    const uint64_t* __restrict__ off, uint64_t n, K flip, C* __restrict__ seg_hist, S* status0, S* status1) {
+  segqueue_body<K, VALS, C, S>(plan, tiles, qtab, off, n, flip, seg_hist, status0, status1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1672,7 +1673,7 @@ ms_status dispatch(const void* kin, const uint32_t* vin, void* kout, uint32_t* v
 // ---------------------------------------------------------------------------
 // Segmented digit passes (long segments).
 struct SegSweepLayout {
-  size_t plan = 0, ctrs = 0, hist = 0, qtab = 0, done = 0, base = 0, chunks = 0, records = 0, status0 = 0, status1 = 0,
+  size_t plan = 0, ctrs = 0, hist = 0, qtab = 0, base = 0, chunks = 0, records = 0, status0 = 0, status1 = 0,
          alt_k = 0, alt_v = 0, total = 0;
   size_t ctrs_hist_bytes = 0, status_bytes = 0;
   uint64_t tiles = 0;  // bound on the tile count: every segment adds at most one partial tile
@@ -1700,13 +1701,11 @@ SegSweepLayout segsweep_layout(ms_key_type kt, bool has_vals, uint64_t n, uint64
   off += align_up(nseg * P * kRadix * cb);
   L.qtab = off;  // one-launch path: queue table
   off += align_up(kQWordsAll * sizeof(uint32_t));
-  L.done = off;  // one-launch path: finished tiles per (segment, phase), a cache line per segment
-  off += align_up(nseg * kDoneWords * sizeof(uint32_t));
   L.ctrs_hist_bytes = off - L.ctrs;
   L.base = off;
   off += align_up(nseg * P * kRadix * cb);
-  L.chunks = off;  // chunk tile starts; per (chunk, queue) starts for the one-launch path
-  off += align_up(static_cast<size_t>(L.num_chunks) * 8 * sizeof(uint64_t));
+  L.chunks = off;  // chunk tile starts
+  off += align_up(static_cast<size_t>(L.num_chunks) * sizeof(uint64_t));
   L.records = off;
   off += align_up(static_cast<size_t>(L.tiles) * sizeof(SegTile));
   L.status_bytes = align_up(static_cast<size_t>(L.tiles) * kRadix * cb);
@@ -1739,6 +1738,33 @@ ms_status launch_segsweep_pass(const SortPlan* plan, int p, const SegTile* recor
   return MS_OK;
 }
 
+// The tile table of the segment passes (1 or 3 launches): records in
+// segment order, the tile count in ctrs[0], the pass plan and, given qtab,
+// the one-launch path's queue starts.
+template <typename K, bool VALS>
+ms_status plan_segment_tiles(const uint64_t* off, uint32_t nseg, uint64_t n, uint32_t tile, char* ws,
+                             const SegSweepLayout& L, const Buffers& buf, uint32_t* qtab, hipStream_t s) {
+  SortPlan* plan = reinterpret_cast<SortPlan*>(ws + L.plan);
+  uint32_t* ctrs = reinterpret_cast<uint32_t*>(ws + L.ctrs);
+  uint64_t* chunk_start = reinterpret_cast<uint64_t*>(ws + L.chunks);
+  SegTile* records = reinterpret_cast<SegTile*>(ws + L.records);
+  uint32_t* wide = ctrs + 1 + kMaxPasses;
+  const uint32_t max_tiles = static_cast<uint32_t>(L.tiles);
+  if (L.num_chunks == 1) {
+    MS_LAUNCH("segsweep_plan", (segsweep_plan1_kernel<K, VALS>), 1, kSegPlanThreads, s, off, nseg, n, tile,
+              max_tiles, wide, ctrs, records, plan, buf, qtab);
+  } else {
+    MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, tile, wide,
+              chunk_start);
+    MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, kSegPlanThreads, s, chunk_start, L.num_chunks,
+              max_tiles, ctrs, plan, buf, qtab);
+    MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, tile,
+              static_cast<const uint64_t*>(chunk_start), max_tiles, wide, records, qtab,
+              static_cast<const uint32_t*>(ctrs));
+  }
+  return MS_OK;
+}
+
 template <typename K, bool VALS, typename C, int THREADS>
 ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
                        uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
@@ -1757,17 +1783,9 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), L.ctrs_hist_bytes / 16,
             reinterpret_cast<uint4*>(ws + L.status0), L.status_bytes / 16);
   Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
-  const uint32_t max_tiles = static_cast<uint32_t>(L.tiles);
-  if (L.num_chunks == 1) {
-    MS_LAUNCH("segsweep_plan", (segsweep_plan1_kernel<K, VALS>), 1, kSegPlanThreads, s, off, nseg, n, kTile,
-              max_tiles, wide, ctrs, records, plan, buf);
-  } else {
-    MS_LAUNCH("segsweep_plan", segsweep_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile, wide,
-              chunk_start);
-    MS_LAUNCH("segsweep_plan", (segsweep_plan_kernel<K, VALS>), 1, kSegPlanThreads, s, chunk_start, L.num_chunks,
-              max_tiles, ctrs, plan, buf);
-    MS_LAUNCH("segsweep_plan", segsweep_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile,
-              static_cast<const uint64_t*>(chunk_start), max_tiles, wide, records);
+  {
+    const ms_status st = plan_segment_tiles<K, VALS>(off, nseg, n, kTile, ws, L, buf, nullptr, s);
+    if (st != MS_OK) return st;
   }
   const uint64_t hblocks = std::min<uint64_t>(L.tiles, 2 * device_cus(256));
   MS_LAUNCH("segsweep_hist", (segsweep_hist_kernel<K, C>), static_cast<uint32_t>(hblocks), 256, s,
@@ -1797,39 +1815,36 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
 
 // The segment passes as one persistent launch (segqueue_kernel), after the
 // clearing and planning launches.  Status words are 64-bit when the list has
-// 2^30 keys or more (a segment might), 32-bit otherwise.  Inputs of at most
-// kOneXcdTiles tiles run on one XCD (one queue), larger ones on every XCD.
-constexpr uint64_t kOneXcdTiles = 256;
-
+// 2^30 keys or more (a segment might), 32-bit otherwise.
 template <typename K, bool VALS, typename C, typename S>
 ms_status run_segqueue(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
                        uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
   constexpr uint32_t kTile = SegSweepCfg::kTile;
-  SortPlan* plan = reinterpret_cast<SortPlan*>(ws + L.plan);
-  uint32_t* ctrs = reinterpret_cast<uint32_t*>(ws + L.ctrs);
   C* hist = reinterpret_cast<C*>(ws + L.hist);
-  uint32_t* done = reinterpret_cast<uint32_t*>(ws + L.done);
-  uint64_t* counts = reinterpret_cast<uint64_t*>(ws + L.chunks);
-  SegTile* records = reinterpret_cast<SegTile*>(ws + L.records);
-  const uint32_t nq = L.tiles <= kOneXcdTiles ? 1u : static_cast<uint32_t>(kMaxQueues);
-  // Counters, histograms and done counts only: a tile clears its own
+  uint32_t* qtab = reinterpret_cast<uint32_t*>(ws + L.qtab);
+  // Counters, histograms and the queue table only: a tile clears its own
   // look-back rows before they are used.
   MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), L.ctrs_hist_bytes / 16,
             static_cast<uint4*>(nullptr), size_t(0));
   Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
-  const uint32_t max_tiles = static_cast<uint32_t>(L.tiles);
-  MS_LAUNCH("segq_plan", segq_count_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile, nq, counts);
-  uint32_t* qtab = reinterpret_cast<uint32_t*>(ws + L.qtab);
-  MS_LAUNCH("segq_plan", (segq_plan_kernel<K, VALS>), 1, kSegPlanThreads, s, counts, L.num_chunks, nq, max_tiles,
-            ctrs, qtab, plan, buf);
-  MS_LAUNCH("segq_plan", segq_fill_kernel, L.num_chunks, kSegPlanThreads, s, off, nseg, n, kTile, nq,
-            static_cast<const uint64_t*>(counts), max_tiles, records);
-  const uint64_t blocks = resident_blocks(reinterpret_cast<const void*>(&segqueue_kernel<K, VALS, C, S>),
-                                          kSegSweepThreads, 256);
-  MS_LAUNCH("segqueue", (segqueue_kernel<K, VALS, C, S>), static_cast<uint32_t>(blocks), kSegSweepThreads, s,
-            static_cast<const SortPlan*>(plan), static_cast<const SegTile*>(records),
-            static_cast<const uint32_t*>(ctrs), qtab, nq, off, n, flip, hist, done,
-            reinterpret_cast<S*>(ws + L.status0), reinterpret_cast<S*>(ws + L.status1));
+  const ms_status st = plan_segment_tiles<K, VALS>(off, nseg, n, kTile, ws, L, buf, qtab, s);
+  if (st != MS_OK) return st;
+  const SortPlan* plan = reinterpret_cast<const SortPlan*>(ws + L.plan);
+  const SegTile* records = reinterpret_cast<const SegTile*>(ws + L.records);
+  S* status0 = reinterpret_cast<S*>(ws + L.status0);
+  S* status1 = reinterpret_cast<S*>(ws + L.status1);
+  // The grid is what the device holds at once: workgroups loop over tickets.
+  if constexpr (sizeof(K) == 4 && !VALS) {
+    const uint64_t blocks = resident_blocks(reinterpret_cast<const void*>(&segqueue_kernel_x2<K, VALS, C, S>),
+                                            kSegSweepThreads, 256);
+    MS_LAUNCH("segqueue", (segqueue_kernel_x2<K, VALS, C, S>), static_cast<uint32_t>(blocks), kSegSweepThreads, s,
+              plan, records, qtab, off, n, flip, hist, status0, status1);
+  } else {
+    const uint64_t blocks = resident_blocks(reinterpret_cast<const void*>(&segqueue_kernel<K, VALS, C, S>),
+                                            kSegSweepThreads, 256);
+    MS_LAUNCH("segqueue", (segqueue_kernel<K, VALS, C, S>), static_cast<uint32_t>(blocks), kSegSweepThreads, s,
+              plan, records, qtab, off, n, flip, hist, status0, status1);
+  }
   return MS_OK;
 }
 

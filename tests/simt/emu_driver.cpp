@@ -96,6 +96,23 @@ static void run_segmented(int kt, const std::vector<uint64_t>& lengths, bool pai
             (!pairs || memcmp(vout.data(), vexp.data(), n * 4) == 0);
   printf("%s sort_segmented kt=%d nseg=%zu n=%zu pairs=%d dist=%s\n", ok ? "ok  " : "FAIL", kt, lengths.size(), n, pairs,
          dist);
+  if (!ok && st == MS_OK) {
+    size_t bad = 0;
+    while (bad < n && kout[bad] == kexp[bad] && (!pairs || vout[bad] == vexp[bad])) ++bad;
+    size_t seg = 0;
+    while (seg + 1 < off.size() && off[seg + 1] <= bad) ++seg;
+    size_t nbad = 0;
+    for (size_t i = 0; i < n; ++i) nbad += kout[i] != kexp[i];
+    printf("     first difference at %zu (segment %zu, offset %zu): got %llu expected %llu; %zu keys differ\n", bad,
+           seg, bad - off[seg], (unsigned long long)kout[bad], (unsigned long long)kexp[bad], nbad);
+    if (getenv("DBGQ"))
+      for (size_t sg = 0; sg + 1 < off.size(); ++sg) {
+        size_t c = 0;
+        for (size_t i = off[sg]; i < off[sg + 1]; ++i) c += kout[i] != kexp[i];
+        printf("     segment %zu [%llu, %llu): %zu differ\n", sg, (unsigned long long)off[sg],
+               (unsigned long long)off[sg + 1], c);
+      }
+  }
   fflush(stdout);
   if (!ok) ++failures;
 }
