@@ -1203,7 +1203,11 @@ __device__ int claim_ticket(uint32_t* qtab, uint32_t nq, uint32_t me, int q, uin
 template <typename K, bool VALS, typename C, typename S>
 __device__ __forceinline__ void segqueue_body(const SortPlan* __restrict__ plan, const SegTile* __restrict__ tiles,
                                               uint32_t* __restrict__ qtab, const uint64_t* __restrict__ off,
-                                              uint64_t n, K flip, C* __restrict__ seg_hist, S* status0, S* status1) {
+                                              uint64_t n, K flip, C* __restrict__ seg_hist, S* status0, S* status1,
+                                              const uint32_t* __restrict__ gate, uint32_t want) {
+  // Lists of 2^30 keys and more launch the queue with both status widths;
+  // the planner's flag (a segment of 2^30 keys or more) lets exactly one run.
+  if (gate != nullptr && *gate != want) return;
   constexpr uint32_t nq = kMaxQueues;
   constexpr int kThreads = kSegSweepThreads;
   constexpr int kKpt = PassCfg<kThreads>::kKpt;
@@ -1447,8 +1451,9 @@ __device__ __forceinline__ void segqueue_body(const SortPlan* __restrict__ plan,
 template <typename K, bool VALS, typename C, typename S>
 __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
     const SortPlan* __restrict__ plan, const SegTile* __restrict__ tiles, uint32_t* __restrict__ qtab,
-    const uint64_t* __restrict__ off, uint64_t n, K flip, C* __restrict__ seg_hist, S* status0, S* status1) {
-  segqueue_body<K, VALS, C, S>(plan, tiles, qtab, off, n, flip, seg_hist, status0, status1);
+    const uint64_t* __restrict__ off, uint64_t n, K flip, C* __restrict__ seg_hist, S* status0, S* status1,
+    const uint32_t* __restrict__ gate, uint32_t want) {
+  segqueue_body<K, VALS, C, S>(plan, tiles, qtab, off, n, flip, seg_hist, status0, status1, gate, want);
 }
 
 // The same for 32-bit keys without values, held to 128 registers so that two
@@ -1457,8 +1462,9 @@ __global__ __launch_bounds__(kSegSweepThreads) void segqueue_kernel(
 template <typename K, bool VALS, typename C, typename S>
 __global__ __launch_bounds__(kSegSweepThreads) __attribute__((amdgpu_waves_per_eu(4))) void segqueue_kernel_x2(
     const SortPlan* __restrict__ plan, const SegTile* __restrict__ tiles, uint32_t* __restrict__ qtab,
-    const uint64_t* __restrict__ off, uint64_t n, K flip, C* __restrict__ seg_hist, S* status0, S* status1) {
-  segqueue_body<K, VALS, C, S>(plan, tiles, qtab, off, n, flip, seg_hist, status0, status1);
+    const uint64_t* __restrict__ off, uint64_t n, K flip, C* __restrict__ seg_hist, S* status0, S* status1,
+    const uint32_t* __restrict__ gate, uint32_t want) {
+  segqueue_body<K, VALS, C, S>(plan, tiles, qtab, off, n, flip, seg_hist, status0, status1, gate, want);
 }
 
 // ---------------------------------------------------------------------------
@@ -1774,7 +1780,6 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   uint32_t* ctrs = reinterpret_cast<uint32_t*>(ws + L.ctrs);
   C* hist = reinterpret_cast<C*>(ws + L.hist);
   C* base = reinterpret_cast<C*>(ws + L.base);
-  uint64_t* chunk_start = reinterpret_cast<uint64_t*>(ws + L.chunks);
   SegTile* records = reinterpret_cast<SegTile*>(ws + L.records);
   char* status[2] = {ws + L.status0, ws + L.status1};
   const uint32_t* num_tiles = ctrs;
@@ -1813,24 +1818,15 @@ ms_status run_segsweep(const void* kin, const uint32_t* vin, void* kout, uint32_
   return MS_OK;
 }
 
-// The segment passes as one persistent launch (segqueue_kernel), after the
-// clearing and planning launches.  Status words are 64-bit when the list has
-// 2^30 keys or more (a segment might), 32-bit otherwise.
+// One launch of the work queue with status words of type S; gate/want as in
+// segqueue_body (nullptr: always runs).
 template <typename K, bool VALS, typename C, typename S>
-ms_status run_segqueue(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
-                       uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
-  constexpr uint32_t kTile = SegSweepCfg::kTile;
-  C* hist = reinterpret_cast<C*>(ws + L.hist);
-  uint32_t* qtab = reinterpret_cast<uint32_t*>(ws + L.qtab);
-  // Counters, histograms and the queue table only: a tile clears its own
-  // look-back rows before they are used.
-  MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), L.ctrs_hist_bytes / 16,
-            static_cast<uint4*>(nullptr), size_t(0));
-  Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
-  const ms_status st = plan_segment_tiles<K, VALS>(off, nseg, n, kTile, ws, L, buf, qtab, s);
-  if (st != MS_OK) return st;
+ms_status launch_segqueue(const uint64_t* off, uint64_t n, K flip, char* ws, const SegSweepLayout& L,
+                          const uint32_t* gate, uint32_t want, hipStream_t s) {
   const SortPlan* plan = reinterpret_cast<const SortPlan*>(ws + L.plan);
   const SegTile* records = reinterpret_cast<const SegTile*>(ws + L.records);
+  uint32_t* qtab = reinterpret_cast<uint32_t*>(ws + L.qtab);
+  C* hist = reinterpret_cast<C*>(ws + L.hist);
   S* status0 = reinterpret_cast<S*>(ws + L.status0);
   S* status1 = reinterpret_cast<S*>(ws + L.status1);
   // The grid is what the device holds at once: workgroups loop over tickets.
@@ -1838,14 +1834,42 @@ ms_status run_segqueue(const void* kin, const uint32_t* vin, void* kout, uint32_
     const uint64_t blocks = resident_blocks(reinterpret_cast<const void*>(&segqueue_kernel_x2<K, VALS, C, S>),
                                             kSegSweepThreads, 256);
     MS_LAUNCH("segqueue", (segqueue_kernel_x2<K, VALS, C, S>), static_cast<uint32_t>(blocks), kSegSweepThreads, s,
-              plan, records, qtab, off, n, flip, hist, status0, status1);
+              plan, records, qtab, off, n, flip, hist, status0, status1, gate, want);
   } else {
     const uint64_t blocks = resident_blocks(reinterpret_cast<const void*>(&segqueue_kernel<K, VALS, C, S>),
                                             kSegSweepThreads, 256);
     MS_LAUNCH("segqueue", (segqueue_kernel<K, VALS, C, S>), static_cast<uint32_t>(blocks), kSegSweepThreads, s,
-              plan, records, qtab, off, n, flip, hist, status0, status1);
+              plan, records, qtab, off, n, flip, hist, status0, status1, gate, want);
   }
   return MS_OK;
+}
+
+// The segment passes as one persistent launch (segqueue_kernel), after the
+// clearing and planning launches.  Segment-local counts fit 30-bit status
+// fields unless a segment has 2^30 keys or more; below 2^30 keys in all no
+// segment can, and only the 32-bit form is launched; otherwise the queue is
+// launched in both widths, the unselected one returning at entry.
+template <typename K, bool VALS, typename C>
+ms_status run_segqueue(const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, const uint64_t* off,
+                       uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
+  constexpr uint32_t kTile = SegSweepCfg::kTile;
+  uint32_t* qtab = reinterpret_cast<uint32_t*>(ws + L.qtab);
+  // Counters, histograms and the queue table only: a tile clears its own
+  // look-back rows before they are used.
+  MS_LAUNCH("clear", clear_kernel, 1024, 256, s, reinterpret_cast<uint4*>(ws + L.ctrs), L.ctrs_hist_bytes / 16,
+            static_cast<uint4*>(nullptr), size_t(0));
+  Buffers buf = {kin, kout, ws + L.alt_k, vin, vout, VALS ? reinterpret_cast<uint32_t*>(ws + L.alt_v) : nullptr};
+  ms_status st = plan_segment_tiles<K, VALS>(off, nseg, n, kTile, ws, L, buf, qtab, s);
+  if (st != MS_OK) return st;
+  if constexpr (sizeof(C) == 8) {
+    if (L.big) {
+      const uint32_t* wide = reinterpret_cast<const uint32_t*>(ws + L.ctrs) + 1 + kMaxPasses;
+      st = launch_segqueue<K, VALS, C, uint32_t>(off, n, flip, ws, L, wide, 0u, s);
+      if (st != MS_OK) return st;
+      return launch_segqueue<K, VALS, C, uint64_t>(off, n, flip, ws, L, wide, 1u, s);
+    }
+  }
+  return launch_segqueue<K, VALS, C, uint32_t>(off, n, flip, ws, L, nullptr, 0u, s);
 }
 
 template <typename K, bool VALS>
@@ -1853,8 +1877,8 @@ ms_status segsweep_dispatch(const void* kin, const uint32_t* vin, void* kout, ui
                             uint32_t nseg, uint64_t n, K flip, char* ws, const SegSweepLayout& L, hipStream_t s) {
   // MS_TUNE_SEG_PASSES = 2: all phases in one persistent launch.
   if (tune_get(MS_TUNE_SEG_PASSES) == 2) {
-    if (L.big) return run_segqueue<K, VALS, uint64_t, uint64_t>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
-    return run_segqueue<K, VALS, uint32_t, uint32_t>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+    if (L.big) return run_segqueue<K, VALS, uint64_t>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
+    return run_segqueue<K, VALS, uint32_t>(kin, vin, kout, vout, off, nseg, n, flip, ws, L, s);
   }
   // 16,384-key tiles only where 1,024 threads fit their registers without
   // spilling: 32-bit keys without values.

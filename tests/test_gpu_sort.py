@@ -14,6 +14,7 @@ import pytest
 import torch
 
 import oracle
+from paper_1105_6040_amd import _native as N
 from paper_1105_6040_amd import api, inputs
 from tests import fullsize
 from tests.oracle_pins import certify_stable_sort
@@ -578,34 +579,48 @@ def test_big_list_sort_pairs_64bit_counters():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("lengths", [[(1 << 30) + 5, 7, 100_000], [70_000, (1 << 30) + 1, 3]])
-def test_big_segment_wide_status(lengths):
+@pytest.mark.parametrize("lengths,seg_passes", [([(1 << 30) + 5, 7, 100_000], 1), ([70_000, (1 << 30) + 1, 3], 1),
+                                                 ([70_000, (1 << 30) + 1, 3], 2)])
+def test_big_segment_wide_status(lengths, seg_passes):
     """A segment of more than 2^30 keys: the planner flags it and the passes
-    run with 64-bit look-back status words (the 32-bit form is launched too
-    and returns at once).  Every segment equals the oracle's sort of it."""
+    (or the one-launch work queue) run with 64-bit look-back status words
+    (the 32-bit form is launched too and returns at once).  Every segment
+    equals the oracle's sort of it."""
     off = inputs.offsets_from_lengths(np.array(lengths))
     n = int(off[-1])
-    say(f"big segment, wide status n={n}")
+    say(f"big segment, wide status n={n} seg_passes={seg_passes}")
     k = _device_keys(n, 33)
-    out = api.sort_segmented(k, dev(off))
-    torch.cuda.synchronize()
+    old = N.tune_get(N.MS_TUNE_SEG_PASSES)
+    N.tune_set(N.MS_TUNE_SEG_PASSES, seg_passes)
+    try:
+        out = api.sort_segmented(k, dev(off))
+        torch.cuda.synchronize()
+    finally:
+        N.tune_set(N.MS_TUNE_SEG_PASSES, old)
     say("big segment: every segment against the oracle")
     fullsize.compare_segments(k, out, off)
     del out, k
     torch.cuda.empty_cache()
 
 
-def test_big_segments_64bit_counters():
-    """Three segments of 2^30 + 11 keys in all (whole-device segment passes
-    with 64-bit bases; every segment below 2^30 keys, so 32-bit look-back
-    status words): every segment equals the oracle's sort of it."""
+@pytest.mark.parametrize("seg_passes", [1, 2])
+def test_big_segments_64bit_counters(seg_passes):
+    """Three segments of 2^30 + 11 keys in all (whole-device segment passes,
+    or the one-launch work queue, with 64-bit bases; every segment below 2^30
+    keys, so 32-bit look-back status words): every segment equals the
+    oracle's sort of it."""
     lengths = [(1 << 29) + 7, 3, (1 << 29) + 1]
     off = inputs.offsets_from_lengths(np.array(lengths))
     n = int(off[-1])
-    say(f"big sort_segmented n={n}")
+    say(f"big sort_segmented n={n} seg_passes={seg_passes}")
     k = _device_keys(n, 32)
-    out = api.sort_segmented(k, dev(off))
-    torch.cuda.synchronize()
+    old = N.tune_get(N.MS_TUNE_SEG_PASSES)
+    N.tune_set(N.MS_TUNE_SEG_PASSES, seg_passes)
+    try:
+        out = api.sort_segmented(k, dev(off))
+        torch.cuda.synchronize()
+    finally:
+        N.tune_set(N.MS_TUNE_SEG_PASSES, old)
     say("big sort_segmented: every segment against the oracle")
     fullsize.compare_segments(k, out, off)
     del out, k
