@@ -1289,28 +1289,40 @@ __device__ __forceinline__ void segqueue_body(const SortPlan* __restrict__ plan,
         }
       } else if (!only) {
         // Phase 0: the tile's counts of every digit added to its segment's
-        // histograms; its look-back rows cleared in both buffers.
+        // histograms; its look-back rows cleared in both buffers.  Keys are
+        // read striped (lane-consecutive, whatever the segment's alignment)
+        // and counted into kCopies copies of the counters, lane l using copy
+        // l % kCopies, so that lanes meeting on a bin rarely share a word.
+        constexpr int kCopies = 32 / P;
+        static_assert(P * kRadix * kCopies * 4 <= kRawBytes, "counter copies fit the stage");
         for (int e = tid; e < kRadix; e += kThreads) {
           status_store(&status0[static_cast<size_t>(i) * kRadix + e], S(0));
           status_store(&status1[static_cast<size_t>(i) * kRadix + e], S(0));
         }
-        for (int e = tid; e < P * kRadix; e += kThreads) s_h[e] = 0;
+        for (int e = tid; e < P * kRadix * kCopies; e += kThreads) s_h[e] = 0;
         __syncthreads();
-        uint32_t unused[kKpt];
-        load_tile_keys<K, false, uint64_t, kKpt>(as_global(static_cast<const K*>(plan->pass[0].src_k)),
-                                                 gptr<const uint32_t>(nullptr),
-                                                 tbeg + static_cast<uint64_t>(tid) * kKpt, tend, K(0), keys, unused);
+        const gptr<const K> hsrc = as_global(static_cast<const K*>(plan->pass[0].src_k)) + tbeg;
 #pragma unroll
         for (int k = 0; k < kKpt; ++k) {
-          if (static_cast<uint32_t>(tid * kKpt + k) < cnt) {
+          const uint32_t e = static_cast<uint32_t>(k * kThreads + tid);
+          keys[k] = e < cnt ? hsrc[e] : K(0);
+        }
+        const uint32_t copy = lane_id() % kCopies;
+#pragma unroll
+        for (int k = 0; k < kKpt; ++k) {
+          if (static_cast<uint32_t>(k * kThreads + tid) < cnt) {
             const K key = flip_key(keys[k], flip);
 #pragma unroll
-            for (int p = 0; p < P; ++p) atomicAdd(&s_h[p * kRadix + digit_of(key, 8 * p)], 1u);
+            for (int p = 0; p < P; ++p) atomicAdd(&s_h[(p * kRadix + digit_of(key, 8 * p)) * kCopies + copy], 1u);
           }
         }
         __syncthreads();
-        for (int e = tid; e < P * kRadix; e += kThreads)
-          if (s_h[e]) atomic_add_c(&h[e], static_cast<C>(s_h[e]));
+        for (int e = tid; e < P * kRadix; e += kThreads) {
+          uint32_t sum = 0;
+#pragma unroll
+          for (int c = 0; c < kCopies; ++c) sum += s_h[e * kCopies + c];
+          if (sum) atomic_add_c(&h[e], static_cast<C>(sum));
+        }
       }
       // Every wave's stores and atomics complete before the item counts
       // itself done (a one-tile segment's later phases have nothing to do).
