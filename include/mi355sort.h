@@ -279,9 +279,12 @@ const char *ms_last_error(void);
  *                         digit passes when the segments average more than
  *                         8,192 keys, one launch per phase; 2: the same
  *                         phases as one persistent launch (a work queue of
- *                         (phase, tile) items, each segment moving to its
- *                         next phase as soon as its previous one is done),
- *                         after the planning launches; 0: every
+ *                         (phase, tile) items in 8 queues of consecutive
+ *                         segments, one per XCD, a queue's items of phase f
+ *                         starting once its phase f - 1 is done), after the
+ *                         planning launches (lists of 2^30 keys and more add
+ *                         a second launch that returns at entry unless a
+ *                         segment has 2^30 keys or more); 0: every
  *                         sort_segmented call is one launch of the
  *                         persistent kernel, whose workgroups each take
  *                         whole segments.

@@ -82,8 +82,11 @@ inline hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int) {
   *v = a == hipDeviceAttributeMultiprocessorCount ? kSimtCUs : 0;
   return hipSuccess;
 }
+// SIMT_BLOCKS_PER_CU (default 1) sets the blocks a CU holds, so that a
+// persistent kernel's grid can be made large enough for its look-back agents.
 inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void*, int, size_t) {
-  *n = 1;
+  const char* e = getenv("SIMT_BLOCKS_PER_CU");
+  *n = e && atoi(e) > 0 ? atoi(e) : 1;
   return hipSuccess;
 }
 

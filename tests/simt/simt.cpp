@@ -120,6 +120,18 @@ void run_fiber(int i) {
   abort();
 }
 
+// Sweeps of a block whose every live thread only spins before the run is
+// declared a livelock (SIMT_LIVELOCK_SWEEPS; blocks that wait on slow
+// neighbours under AddressSanitizer may need more than the default).
+long livelock_sweeps() {
+  static const long v = [] {
+    const char* e = getenv("SIMT_LIVELOCK_SWEEPS");
+    const long x = e ? atol(e) : 0;
+    return x > 0 ? x : 20000000L;
+  }();
+  return v;
+}
+
 void run_block() {
   const int n = static_cast<int>(g.f.size());
   const int nwaves = (n + 63) / 64;
@@ -200,7 +212,7 @@ void run_block() {
       idle_sweeps = 0;
     } else if (any_live) {
       if (!any_yield) die("deadlock: threads wait on a barrier or collective others never reach");
-      if (++idle_sweeps > 20000000) die("livelock: threads spin on data no running block will write");
+      if (++idle_sweeps > livelock_sweeps()) die("livelock: threads spin on data no running block will write");
       if (idle_sweeps % 64 == 0) sched_yield();
     }
   }
