@@ -404,9 +404,9 @@ def test_sort_segmented_many_long_segments(nseg, nlong, threads):
 def test_sort_segmented_work_queue(dt, nseg, nlong):
     """MS_TUNE_SEG_PASSES = 2: every phase of the segment passes (histogram,
     P digit passes; one-tile segments sorted whole) in one persistent launch,
-    each segment going on to its next phase as soon as its previous one is
-    done.  Keys and pairs against the oracle, over one and several planning
-    chunks."""
+    each queue of consecutive segments going on to its next phase once its
+    previous one is done.  Keys and pairs against the oracle, over one and
+    several planning chunks."""
     from paper_1105_6040_amd import _native as N
     lengths = many_segment_lengths(nseg, nlong, nseg + 7)
     if nseg == 7:
@@ -424,6 +424,40 @@ def test_sort_segmented_work_queue(dt, nseg, nlong):
         ko, vo = api.sort_segmented(dev(k), dev(off), dev(v))
         ek, ev = oracle.sort_segmented(k, off, v)
         assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev), nseg
+    finally:
+        N.tune_set(N.MS_TUNE_SEG_PASSES, old)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_sort_segmented_work_queue_random_mix(seed):
+    """The one-launch queue on seeded mixes of segment lengths around its
+    boundaries (empty, one key, one tile exactly, one key past a tile, a
+    few tiles, long ones), so that queue starts, one-tile segments and
+    ragged last tiles fall everywhere; key types and values vary with the
+    seed.  Every segment against the oracle."""
+    rng = np.random.default_rng([11, seed])
+    nseg = int(rng.integers(2, 48))
+    pool = np.array([0, 1, 7, 8191, 8192, 8193, 16384, 16385, 24_000, 65_537, 150_000, 300_000])
+    lengths = rng.choice(pool, size=nseg).astype(np.int64)
+    lengths[rng.integers(0, nseg)] = 200_000 + int(rng.integers(0, 8192))
+    while lengths.sum() <= 8192 * nseg:  # the segment passes take averages above one tile
+        lengths[rng.integers(0, nseg)] += 100_000
+    off = inputs.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    assert n > 8192 * nseg
+    dt = ("i32", "u32", "u64")[seed % 3]
+    say(f"work queue mix seed={seed} {dt} nseg={nseg} n={n}")
+    k = inputs.keys(dt, n, ("uniform", "few", "bits16")[(seed // 3) % 3], seed=seed + 40)
+    v = np.arange(n, dtype=np.uint32) if seed % 2 else None
+    old = N.tune_get(N.MS_TUNE_SEG_PASSES)
+    N.tune_set(N.MS_TUNE_SEG_PASSES, 2)
+    try:
+        if v is None:
+            assert np.array_equal(host(api.sort_segmented(dev(k), dev(off))), oracle.sort_segmented(k, off))
+        else:
+            ko, vo = api.sort_segmented(dev(k), dev(off), dev(v))
+            ek, ev = oracle.sort_segmented(k, off, v)
+            assert np.array_equal(host(ko), ek) and np.array_equal(host(vo), ev)
     finally:
         N.tune_set(N.MS_TUNE_SEG_PASSES, old)
 
