@@ -635,7 +635,9 @@ def serving_workload(dev, nreq=2000, warm=200, seed=0):
     every request arriving at once; both then run the same Poisson trace at
     0.8 x the one-launch-per-request server's capacity (warm + nreq requests,
     the first `warm` excluded from the figures).  The continuous-batching
-    server's bound on queued steps is tuned on a trace of another seed."""
+    server's parameters (steps queued ahead; the length above which a request
+    takes a launch of its own beside the steps, and how many such launches run
+    at once) are tuned on a Poisson trace of another seed at the same rate."""
     import numpy as np
     import torch
 
@@ -653,11 +655,14 @@ def serving_workload(dev, nreq=2000, warm=200, seed=0):
     free, _ = torch.cuda.mem_get_info(dev)
     budget = max(1 << 30, free - (16 << 30))
 
-    def run(kind, arrivals, steps_inflight=2, lens=lengths):
+    def run(kind, arrivals, params=(2, None, 2), lens=lengths):
         reqs = serve.make_requests(arrivals, lens)
         if kind == "step":
+            steps_inflight, above, dinf = params
             ex = serve.GpuStepExecutor(keys, vals, ok, ov)
-            srv = serve.StepServer(ex, budget_bytes=budget, max_steps_inflight=steps_inflight)
+            dx = serve.GpuExecutor(keys, vals, ok, ov, streams=2) if above is not None else None
+            srv = serve.StepServer(ex, budget_bytes=budget, max_steps_inflight=steps_inflight, direct=dx,
+                                   direct_above=above, direct_inflight=dinf)
         else:
             ex = serve.GpuExecutor(keys, vals, ok, ov, streams=2)
             srv = serve.Server(ex, budget_bytes=budget, max_inflight=4, streams=2)
@@ -677,32 +682,34 @@ def serving_workload(dev, nreq=2000, warm=200, seed=0):
 
     at_once = [0.0] * total_req
     run("single", at_once)  # warm-up of both paths
-    run("step", at_once)
-    cap = {}
-    for kind in ("single", "step"):
-        st, reqs = run(kind, at_once)
-        cap[kind] = summary(st, reqs)
-    rate = 0.8 * cap["single"]["req_per_s"]
+    run("step", at_once, (2, 100_000, 2))
+    cap = {"one_launch_per_request": summary(*run("single", at_once))}
+    rate = 0.8 * cap["one_launch_per_request"]["req_per_s"]
 
     def poisson(s):
         g2 = inputs.rng("serving", s)
         gaps = g2.exponential(1.0 / rate, total_req)
         return list(gaps.cumsum() - gaps[0])
 
-    # Tune the queued-step bound on a trace of another seed (its own lengths too).
+    # Tune on a trace of another seed (its own lengths too) at the same rate.
     _, tl = inputs.serving_trace(seed=seed + 1, nreq=total_req, rate_per_s=1.0)
     tl = np.minimum(tl, lengths)  # fits the staged pool request by request
-    tuned = tune.Tuner(cache_path=None).tune_serving(
-        lambda c: run("step", poisson(seed + 101), c, tl)[0])
-    best = tuned["params"][0]
+    tune_arrivals = poisson(seed + 101)
+    tuned = tune.Tuner(cache_path=None).tune_serving(lambda c: run("step", tune_arrivals, c, tl)[0])
+    best = tuple(tuned["params"])
+    cap["continuous_batching"] = summary(*run("step", at_once, best))
+    cap["continuous_batching_steps_only"] = summary(*run("step", at_once, (best[0], None, 2)))
     arrivals = poisson(seed + 1)
     per_req = summary(*run("single", arrivals))
     batched = summary(*run("step", arrivals, best))
+    steps_only = summary(*run("step", arrivals, (best[0], None, 2)))
     return {"requests_measured": nreq, "warmup_requests": warm, "pairs_staged": total,
-            "closed_loop_capacity": {"one_launch_per_request": cap["single"], "continuous_batching": cap["step"]},
-            "rate_req_per_s": round(rate, 1), "continuous_batching_steps_inflight": best,
-            "steps_inflight_trials_p99_p50_ms": tuned["trials"],
-            "one_launch_per_request": per_req, "continuous_batching": batched}
+            "closed_loop_capacity": cap, "rate_req_per_s": round(rate, 1),
+            "continuous_batching_params": {"steps_inflight": best[0], "direct_above_pairs": best[1],
+                                           "direct_inflight": best[2]},
+            "tuning_trials_params_p99_p50_ms": tuned["trials"],
+            "one_launch_per_request": per_req, "continuous_batching": batched,
+            "continuous_batching_steps_only": steps_only}
 
 
 if __name__ == "__main__":

@@ -22,6 +22,12 @@ Two servers share the request model and the statistics:
     queued on the device (steps of one request run in stream order, so the
     host never waits for a step before queueing the next one).
 
+  Optionally (``direct`` + ``direct_above``) requests longer than a threshold
+  skip the steps: each is one launch of its whole sort on streams of its own,
+  admitted by the same HBM budget from a queue of its own, and runs on the
+  device beside the steps.  A step then lasts as long as the phases of the
+  short requests in it, not of the longest one admitted.
+
 ``Server`` -- the baseline: one launch per request (sort_pairs), the same
   admission by workspace bytes, launches round robin over a few streams.
 
@@ -147,28 +153,42 @@ class StepExecutor:
 
 class StepServer:
     def __init__(self, executor: StepExecutor, budget_bytes: int, max_active: int = 1024,
-                 max_steps_inflight: int = 2, clock=time.perf_counter):
+                 max_steps_inflight: int = 2, clock=time.perf_counter, direct: "Executor" = None,
+                 direct_above: int = None, direct_inflight: int = 2):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_active = min(int(max_active), executor.max_requests_per_step)
         self.max_steps_inflight = int(max_steps_inflight)
         self.clock = clock
+        # Requests of more than `direct_above` pairs skip the steps: each is
+        # one launch of its whole sort on the `direct` executor's streams,
+        # running beside the steps (at most `direct_inflight` at once).
+        self.direct = direct if direct_above is not None else None
+        self.direct_above = direct_above
+        self.direct_inflight = max(1, int(direct_inflight))
 
     def run(self, reqs: List[Request]) -> ServeStats:
         reqs = sorted(reqs, key=lambda r: r.arrival)
+        dx = self.direct
         for r in reqs:
-            r.phases, r.work_bytes = self.ex.plan(r.n)
+            if dx is not None and r.n > self.direct_above:
+                r.path = "single"
+                r.phases, r.work_bytes = 0, dx.workspace_bytes(r.n)
+            else:
+                r.path = "step"
+                r.phases, r.work_bytes = self.ex.plan(r.n)
             r.phase = 0
-            r.path = "step"
-        queue: "collections.deque[Request]" = collections.deque()
+        queue: "collections.deque[Request]" = collections.deque()   # waiting for steps
+        dqueue: "collections.deque[Request]" = collections.deque()  # waiting for a launch of their own
         active: List[Request] = []
         inflight: "collections.deque" = collections.deque()  # (handle, requests finishing in that step)
-        used = i = done = steps = waits = max_used = max_seen = max_act = 0
+        dinflight: List[tuple] = []                          # (handle, request) of direct launches
+        used = i = done = steps = waits = max_used = max_seen = max_act = dlaunches = slot = 0
         t0 = self.clock()
         while done < len(reqs):
             now = self.clock() - t0
             while i < len(reqs) and reqs[i].arrival <= now:
-                queue.append(reqs[i])
+                (dqueue if reqs[i].path == "single" else queue).append(reqs[i])
                 i += 1
             # Retire, in step order, what the device has finished.
             while inflight and self.ex.finished(inflight[0][0]):
@@ -179,12 +199,23 @@ class StepServer:
                     used -= r.work_bytes
                     self.ex.release(r)
                 done += len(fin)
+            if dinflight:
+                still = []
+                for h, r in dinflight:
+                    if dx.finished(h):
+                        r.done = self.clock() - t0
+                        used -= r.work_bytes
+                        dx.release(h)
+                        done += 1
+                    else:
+                        still.append((h, r))
+                dinflight = still
             # Admit into free slots and memory; an empty device always takes
             # the head request (so that a request above the budget still runs).
             blocked = False
             while queue and len(active) < self.max_active:
                 r = queue[0]
-                if used + r.work_bytes > self.budget and (active or inflight):
+                if used + r.work_bytes > self.budget and (active or inflight or dinflight):
                     blocked = True
                     break
                 queue.popleft()
@@ -193,6 +224,18 @@ class StepServer:
                 max_used = max(max_used, used)
                 r.launched = self.clock() - t0
                 active.append(r)
+            while dqueue and len(dinflight) < self.direct_inflight:
+                r = dqueue[0]
+                if used + r.work_bytes > self.budget and (active or inflight or dinflight):
+                    blocked = True
+                    break
+                dqueue.popleft()
+                used += r.work_bytes
+                max_used = max(max_used, used)
+                r.launched = self.clock() - t0
+                dinflight.append((dx.launch(r, slot), r))
+                slot += 1
+                dlaunches += 1
             if blocked:
                 waits += 1
             if active and len(inflight) < self.max_steps_inflight:
@@ -207,12 +250,14 @@ class StepServer:
                 max_act = max(max_act, len(active))
                 active = keep
                 continue
-            if not active and not inflight and not queue and i < len(reqs):
+            if not (active or inflight or dinflight or queue or dqueue) and i < len(reqs):
                 wait = reqs[i].arrival - (self.clock() - t0)
                 if wait > 0:
                     time.sleep(min(wait, 0.0005))
         self.ex.join()
-        return _stats(reqs, steps, max_seen, waits, max_used, max_act)
+        if dx is not None:
+            dx.join()
+        return _stats(reqs, steps + dlaunches, max_seen, waits, max_used, max_act)
 
 
 class FakeStepExecutor(StepExecutor):

@@ -44,6 +44,21 @@ SEG_PASS_THREADS = (512, 1024)
 # segments averaging more than this many keys (mi355sort.h).
 SEG_PASS_MIN_AVERAGE = 8192
 SERVE_STEPS_INFLIGHT = (1, 2, 3)
+# Continuous-batching server: requests above this many pairs take a launch of
+# their own beside the steps (None: every request is batched), and how many of
+# those launches may run at once.
+SERVE_DIRECT_ABOVE = (None, 10_000, 30_000, 100_000, 300_000, 1_000_000)
+SERVE_DIRECT_INFLIGHT = (2, 4)
+
+
+def serving_candidates():
+    """(steps queued ahead, direct threshold, direct launches in flight)."""
+    out = []
+    for si in SERVE_STEPS_INFLIGHT:
+        for above in SERVE_DIRECT_ABOVE:
+            for dinf in (SERVE_DIRECT_INFLIGHT if above is not None else SERVE_DIRECT_INFLIGHT[:1]):
+                out.append((si, above, dinf))
+    return out
 
 
 def uses_segment_passes(n: int, nseg: int) -> bool:
@@ -173,20 +188,21 @@ class Tuner:
 
         return self._search(key + "|v3", space, apply, run, force)
 
-    def tune_serving(self, run_server: Callable[[int], "object"], force: bool = False,
-                     candidates: Iterable[int] = SERVE_STEPS_INFLIGHT) -> dict:
-        """Pick the continuous-batching server's bound on queued steps with the
-        lowest p99 latency; run_server(steps) must run a short trace (not the
-        one that is reported) and return ServeStats."""
-        key = f"{self._device()}|serving|steps"
+    def tune_serving(self, run_server: Callable[[tuple], "object"], force: bool = False,
+                     candidates: Optional[Iterable[tuple]] = None) -> dict:
+        """Pick the continuous-batching server's parameters (steps queued
+        ahead, direct threshold, direct launches in flight) with the lowest
+        p99 latency; run_server(params) must run a short trace (not the one
+        that is reported) and return ServeStats."""
+        key = f"{self._device()}|serving|steps_direct"
         if not force and key in self.cache:
             return self.cache[key]
         trials = []
-        for c in candidates:
-            st = run_server(c)
-            trials.append((st.p99_ms, st.p50_ms, c))
-        trials.sort()
-        rec = {"params": [trials[0][2]], "p99_ms": round(trials[0][0], 4),
+        for c in (serving_candidates() if candidates is None else candidates):
+            st = run_server(tuple(c))
+            trials.append((st.p99_ms, st.p50_ms, list(c)))
+        trials.sort(key=lambda t: (t[0], t[1]))
+        rec = {"params": trials[0][2], "p99_ms": round(trials[0][0], 4),
                "trials": [[c, round(p99, 4), round(p50, 4)] for p99, p50, c in trials]}
         self.cache[key] = rec
         self._save()

@@ -99,7 +99,7 @@ def _check_every_request(reqs, keys, vals, tk, tv, out_k, out_v, alone=True):
             assert np.array_equal(ak.cpu().numpy(), ek) and np.array_equal(av.cpu().numpy(), ev), r.rid
 
 
-@pytest.mark.parametrize("server", ["step", "one_launch"])
+@pytest.mark.parametrize("server", ["step", "step_direct", "one_launch"])
 def test_serving_results_alone_and_in_the_mix(server):
     reqs, keys, vals = staged()
     dev = torch.device("cuda:0")
@@ -111,6 +111,15 @@ def test_serving_results_alone_and_in_the_mix(server):
         stats = serve.StepServer(ex, budget_bytes=1 << 34).run(reqs)
         assert stats.launches < 5 * len(reqs)
         assert stats.max_active > 1
+    elif server == "step_direct":
+        # Long requests as launches of their own beside the steps of the rest.
+        ex = serve.GpuStepExecutor(tk, tv, ok, ov)
+        dx = serve.GpuExecutor(tk, tv, ok, ov, streams=2)
+        stats = serve.StepServer(ex, budget_bytes=1 << 34, direct=dx, direct_above=30_000, direct_inflight=4).run(reqs)
+        paths = {r.path for r in reqs}
+        assert paths == {"step", "single"}, paths
+        assert all((r.path == "single") == (r.n > 30_000) for r in reqs)
+        assert stats.max_active > 1
     else:
         ex = serve.GpuExecutor(tk, tv, ok, ov, streams=2)
         stats = serve.Server(ex, budget_bytes=1 << 34).run(reqs)
@@ -121,7 +130,7 @@ def test_serving_results_alone_and_in_the_mix(server):
     _check_every_request(reqs, keys, vals, tk, tv, ok.cpu().numpy(), ov.cpu().numpy())
 
 
-@pytest.mark.parametrize("server", ["step", "one_launch"])
+@pytest.mark.parametrize("server", ["step", "step_direct", "one_launch"])
 def test_serving_under_an_hbm_cap(server):
     """Everything arrives at once and the budget holds about three requests'
     state: admission waits for memory, results are unchanged."""
@@ -134,6 +143,13 @@ def test_serving_under_an_hbm_cap(server):
         budget = 3 * N.step_plan(N.MS_KEY_U32, True, big)[1]
         ex = serve.GpuStepExecutor(tk, tv, ok, ov)
         stats = serve.StepServer(ex, budget_bytes=budget).run(reqs)
+    elif server == "step_direct":
+        budget = 3 * max(N.step_plan(N.MS_KEY_U32, True, big)[1],
+                         N.workspace_size(N.MS_OP_SORT_PAIRS, N.MS_KEY_U32, True, big))
+        ex = serve.GpuStepExecutor(tk, tv, ok, ov)
+        dx = serve.GpuExecutor(tk, tv, ok, ov, streams=2)
+        stats = serve.StepServer(ex, budget_bytes=budget, direct=dx, direct_above=30_000,
+                                 direct_inflight=4).run(reqs)
     else:
         budget = 3 * N.workspace_size(N.MS_OP_SORT_PAIRS, N.MS_KEY_U32, True, big)
         ex = serve.GpuExecutor(tk, tv, ok, ov, streams=2)

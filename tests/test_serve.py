@@ -103,3 +103,33 @@ def test_one_launch_server_respects_the_budget():
     biggest = max(ex.workspace_bytes(r.n) for r in reqs)
     assert stats.max_reserved_bytes <= max(budget, biggest)
     assert stats.budget_waits > 0
+
+
+def test_step_server_gives_long_requests_a_launch_of_their_own():
+    """Requests above the threshold run as one launch each beside the steps;
+    the rest are batched; every result is the oracle's."""
+    reqs, keys, vals = _trace(nreq=150, rate=5e4)
+    ex = serve.FakeStepExecutor(keys, vals, _oracle_sort, small=5000)
+    dx = serve.FakeExecutor(keys, vals, _oracle_sort)
+    dx.out_k, dx.out_v = ex.out_k, ex.out_v  # one output pool for both paths
+    stats = serve.StepServer(ex, budget_bytes=1 << 30, direct=dx, direct_above=20000).run(reqs)
+    _check_results(reqs, ex, keys, vals)
+    for r in reqs:
+        assert r.path == ("single" if r.n > 20000 else "step"), (r.rid, r.n, r.path)
+    long_ids = {r.rid for r in reqs if r.n > 20000}
+    assert long_ids and len(long_ids) < len(reqs)
+    assert all(rid not in long_ids for step in ex.phase_log for rid, _ in step)
+    assert stats.launches == len(ex.phase_log) + len(long_ids)
+
+
+def test_step_server_with_direct_launches_respects_the_budget():
+    reqs, keys, vals = _trace(nreq=120, rate=1e6)  # everything arrives at once
+    ex = serve.FakeStepExecutor(keys, vals, _oracle_sort, seconds_per_pair=2e-8, small=5000)
+    dx = serve.FakeExecutor(keys, vals, _oracle_sort, seconds_per_pair=2e-8)
+    dx.out_k, dx.out_v = ex.out_k, ex.out_v
+    budget = 3 * 8 * 60000
+    stats = serve.StepServer(ex, budget_bytes=budget, direct=dx, direct_above=30000, direct_inflight=3).run(reqs)
+    biggest = max(max(ex.plan(r.n)[1], dx.workspace_bytes(r.n)) for r in reqs)
+    assert stats.max_reserved_bytes <= max(budget, biggest)
+    assert stats.budget_waits > 0
+    _check_results(reqs, ex, keys, vals)
