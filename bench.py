@@ -253,6 +253,8 @@ def main():
     ap.add_argument("--segments", action="store_true",
                     help="instead of the headline: the 50,000-segment batched sort alone")
     ap.add_argument("--serving", action="store_true", help="instead of the headline: the serving stream alone")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="measured requests of the serving stream (after 200 warm-up ones)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (no multi-GPU path is built)",
@@ -275,10 +277,13 @@ def main():
         print(json.dumps(process_sweep(dev, stream)), flush=True)
         return
     if args.segments:
-        print(json.dumps({"segments_50k": segments_workload(dev, stream, tune_it=not args.no_tune)}), flush=True)
+        print(json.dumps({"segments_50k": segments_workload(dev, stream, tune_it=not args.no_tune),
+                          "segments_50k_hi19023": segments_workload(dev, stream, tune_it=not args.no_tune,
+                                                                    hi=19_023)}), flush=True)
         return
     if args.serving:
-        print(json.dumps({"serving": serving_workload(dev)}), flush=True)
+        print(json.dumps({"serving": serving_workload(dev, nreq=args.serving_requests,
+                                                      tune_it=not args.no_tune)}), flush=True)
         return
     n = 1 << 28
     log("generating 2^28 int32 uniform keys")
@@ -398,7 +403,10 @@ def extra_workloads(args, dev, stream):
 
     ex["paper_small_p4"] = paper_small_workload(dev, stream)
     ex["segments_50k"] = segments_workload(dev, stream, tune_it=not args.no_tune)
-    ex["serving"] = serving_workload(dev)
+    # The batched configuration's stated total (~2^27 keys) with its segment
+    # count: lengths log-uniform in [16, 19,023].
+    ex["segments_50k_hi19023"] = segments_workload(dev, stream, tune_it=not args.no_tune, hi=19_023)
+    ex["serving"] = serving_workload(dev, nreq=args.serving_requests, tune_it=not args.no_tune)
     return ex
 
 
@@ -570,19 +578,21 @@ def process_sweep(dev, stream, reps=20, warmup=5):
             "data": "synthetic int32 uniform [0, 2^31), seed 0", "rows": rows}
 
 
-def segments_workload(dev, stream, seed=0, tune_it=True):
-    """50,000 segments, lengths log-uniform in [16, 10^6] (about 4.5e9 int32
-    keys, uniform in [0, 2^31), drawn on the device from a seeded generator),
-    one sort_segmented call, on each of its three paths: the work queue (one
-    persistent launch for every phase), the segment passes (a launch per
-    phase) and the persistent kernel with one workgroup per segment."""
+def segments_workload(dev, stream, seed=0, tune_it=True, hi=1_000_000):
+    """50,000 segments, lengths log-uniform in [16, hi] (hi = 10^6: about
+    4.5e9 int32 keys; hi = 19,023: about 2^27, the total the batched
+    configuration states), keys uniform in [0, 2^31) drawn on the device from
+    a seeded generator, one sort_segmented call on each path that applies:
+    the work queue (one persistent launch for every phase), the segment
+    passes (a launch per phase) and the persistent kernel with one workgroup
+    per segment (segments averaging at most 8,192 keys take only the last)."""
     import torch
 
     from paper_1105_6040_amd import _native as N
     from paper_1105_6040_amd import api, inputs, tune
 
-    log("segments: 50,000 log-uniform [16, 1e6]")
-    lengths = inputs.segment_lengths(seed)
+    log(f"segments: 50,000 log-uniform [16, {hi}]")
+    lengths = inputs.segment_lengths(seed, hi=hi)
     off = inputs.offsets_from_lengths(lengths)
     n = int(off[-1])
     g = torch.Generator(device=dev)
@@ -595,7 +605,10 @@ def segments_workload(dev, stream, seed=0, tune_it=True):
     run = lambda: api.sort_segmented(k, toff, keys_out=out, ws=ws)  # noqa: E731
     paths = {}
     saved = N.tune_get(N.MS_TUNE_SEG_PASSES)
-    for mode, name in ((2, "work_queue_one_launch"), (1, "segment_passes"), (0, "persistent_one_wg_per_segment")):
+    modes = ((2, "work_queue_one_launch"), (1, "segment_passes"), (0, "persistent_one_wg_per_segment"))
+    if not tune.uses_segment_passes(n, int(lengths.size)):
+        modes = modes[2:]
+    for mode, name in modes:
         N.tune_set(N.MS_TUNE_SEG_PASSES, mode)
         _, per = time_steps(run, 3, 1, stream)
         N.timing_reset()
@@ -621,14 +634,15 @@ def segments_workload(dev, stream, seed=0, tune_it=True):
     res.update({"ms_median": round(ms, 3), "path": {0: "persistent", 1: "segment passes", 2: "work queue"}[
         N.tune_get(N.MS_TUNE_SEG_PASSES)], "GKeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
         "GBps_at_36B_per_key": round(n * 36 / (ms * 1e-3) / 1e9, 1)})
-    q = paths["work_queue_one_launch"]["ms_median"]
-    res["work_queue_GBps_at_36B_per_key"] = round(n * 36 / (q * 1e-3) / 1e9, 1)
+    if "work_queue_one_launch" in paths:
+        q = paths["work_queue_one_launch"]["ms_median"]
+        res["work_queue_GBps_at_36B_per_key"] = round(n * 36 / (q * 1e-3) / 1e9, 1)
     del k, out, ws, toff
     torch.cuda.empty_cache()
     return res
 
 
-def serving_workload(dev, nreq=2000, warm=200, seed=0):
+def serving_workload(dev, nreq=2000, warm=200, seed=0, tune_it=True):
     """Serving stream: requests of (uint32 key, uint32 value) pairs, lengths
     log-uniform in [1e3, 1e7], keys uniform, payloads staged on the device
     before the clock.  Each server's closed-loop capacity is measured with
@@ -637,7 +651,9 @@ def serving_workload(dev, nreq=2000, warm=200, seed=0):
     the first `warm` excluded from the figures).  The continuous-batching
     server's parameters (steps queued ahead; the length above which a request
     takes a launch of its own beside the steps, and how many such launches run
-    at once) are tuned on a Poisson trace of another seed at the same rate."""
+    at once) are tuned on a Poisson trace of another seed at the same rate
+    (without tuning: 2 steps ahead, requests above 10^6 pairs on launches of
+    their own, 2 of those at once)."""
     import numpy as np
     import torch
 
@@ -695,7 +711,10 @@ def serving_workload(dev, nreq=2000, warm=200, seed=0):
     _, tl = inputs.serving_trace(seed=seed + 1, nreq=total_req, rate_per_s=1.0)
     tl = np.minimum(tl, lengths)  # fits the staged pool request by request
     tune_arrivals = poisson(seed + 101)
-    tuned = tune.Tuner(cache_path=None).tune_serving(lambda c: run("step", tune_arrivals, c, tl)[0])
+    if tune_it:
+        tuned = tune.Tuner(cache_path=None).tune_serving(lambda c: run("step", tune_arrivals, c, tl)[0])
+    else:
+        tuned = {"params": [2, 1_000_000, 2], "trials": []}
     best = tuple(tuned["params"])
     cap["continuous_batching"] = summary(*run("step", at_once, best))
     cap["continuous_batching_steps_only"] = summary(*run("step", at_once, (best[0], None, 2)))

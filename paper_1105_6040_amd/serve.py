@@ -44,6 +44,8 @@ import math
 import time
 from typing import Dict, List, Sequence
 
+from . import markers
+
 
 @dataclasses.dataclass
 class Request:
@@ -58,6 +60,7 @@ class Request:
     phase: int = 0          # next phase to run (StepServer)
     work: object = None     # executor's per-request state (StepServer)
     work_bytes: int = 0
+    marker: int = 0         # roctx range of the request (markers.py)
 
     @property
     def latency(self) -> float:
@@ -181,7 +184,7 @@ class StepServer:
         queue: "collections.deque[Request]" = collections.deque()   # waiting for steps
         dqueue: "collections.deque[Request]" = collections.deque()  # waiting for a launch of their own
         active: List[Request] = []
-        inflight: "collections.deque" = collections.deque()  # (handle, requests finishing in that step)
+        inflight: "collections.deque" = collections.deque()  # (handle, requests finishing in that step, marker)
         dinflight: List[tuple] = []                          # (handle, request) of direct launches
         used = i = done = steps = waits = max_used = max_seen = max_act = dlaunches = slot = 0
         t0 = self.clock()
@@ -192,12 +195,14 @@ class StepServer:
                 i += 1
             # Retire, in step order, what the device has finished.
             while inflight and self.ex.finished(inflight[0][0]):
-                _, fin = inflight.popleft()
+                _, fin, mk = inflight.popleft()
                 t = self.clock() - t0
+                markers.stop(mk)
                 for r in fin:
                     r.done = t
                     used -= r.work_bytes
                     self.ex.release(r)
+                    markers.stop(r.marker)
                 done += len(fin)
             if dinflight:
                 still = []
@@ -206,6 +211,7 @@ class StepServer:
                         r.done = self.clock() - t0
                         used -= r.work_bytes
                         dx.release(h)
+                        markers.stop(r.marker)
                         done += 1
                     else:
                         still.append((h, r))
@@ -223,6 +229,7 @@ class StepServer:
                 used += r.work_bytes
                 max_used = max(max_used, used)
                 r.launched = self.clock() - t0
+                r.marker = markers.start(f"request {r.rid} n={r.n} step")
                 active.append(r)
             while dqueue and len(dinflight) < self.direct_inflight:
                 r = dqueue[0]
@@ -233,19 +240,21 @@ class StepServer:
                 used += r.work_bytes
                 max_used = max(max_used, used)
                 r.launched = self.clock() - t0
+                r.marker = markers.start(f"request {r.rid} n={r.n} single")
                 dinflight.append((dx.launch(r, slot), r))
                 slot += 1
                 dlaunches += 1
             if blocked:
                 waits += 1
             if active and len(inflight) < self.max_steps_inflight:
+                mk = markers.start(f"step {steps} requests={len(active)}")
                 h = self.ex.step(active)
                 steps += 1
                 fin, keep = [], []
                 for r in active:
                     r.phase += 1
                     (fin if r.phase >= r.phases else keep).append(r)
-                inflight.append((h, fin))
+                inflight.append((h, fin, mk))
                 max_seen = max(max_seen, len(inflight))
                 max_act = max(max_act, len(active))
                 active = keep
@@ -428,6 +437,7 @@ class Server:
                     done += 1
                     used -= reserved
                     self.ex.release(h)
+                    markers.stop(r.marker)
                 else:
                     still.append((h, r, reserved))
             inflight = still
@@ -441,6 +451,7 @@ class Server:
                 queue.popleft()
                 r.launched = self.clock() - t0
                 r.path = "single"
+                r.marker = markers.start(f"request {r.rid} n={r.n} single")
                 h = self.ex.launch(r, slot % self.streams)
                 slot += 1
                 launches += 1

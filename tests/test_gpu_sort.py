@@ -689,3 +689,21 @@ def test_segments_workload_full_size():
         N.tune_set(N.MS_TUNE_SEG_PASSES, old)
     del out, k
     torch.cuda.empty_cache()
+
+
+def test_segments_workload_stated_total():
+    """The batched workload's segment count at the total it states (~2^27
+    keys): 50,000 segments, lengths log-uniform in [16, 19,023], int32 keys
+    uniform in [0, 2^31), as the benchmark runs it; every segment equals the
+    oracle's sort of the same keys."""
+    lengths = inputs.segment_lengths(0, hi=19_023)
+    off = inputs.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    say(f"segments workload [16, 19023] n={n} nseg={lengths.size}")
+    k = _device_keys(n, 0)
+    out = api.sort_segmented(k, dev(off))
+    torch.cuda.synchronize()
+    say(f"all {lengths.size} segments against the oracle on {fullsize.THREADS} host threads")
+    assert fullsize.compare_segments(k, out, off) == lengths.size
+    del out, k
+    torch.cuda.empty_cache()

@@ -133,3 +133,45 @@ def test_step_server_with_direct_launches_respects_the_budget():
     assert stats.max_reserved_bytes <= max(budget, biggest)
     assert stats.budget_waits > 0
     _check_results(reqs, ex, keys, vals)
+
+
+def test_markers_cover_every_request_and_step(monkeypatch):
+    """With markers on, every request and every step opens one roctx range
+    and closes it once; results are unchanged."""
+    from paper_1105_6040_amd import markers
+    opened, closed = {}, []
+    counter = iter(range(1, 1 << 30))
+
+    def start(msg):
+        i = next(counter)
+        opened[i] = msg
+        return i
+
+    monkeypatch.setattr(markers, "start", start)
+    monkeypatch.setattr(markers, "stop", lambda i: closed.append(i))
+    reqs, keys, vals = _trace(nreq=80, rate=5e4)
+    ex = serve.FakeStepExecutor(keys, vals, _oracle_sort, small=5000)
+    dx = serve.FakeExecutor(keys, vals, _oracle_sort)
+    dx.out_k, dx.out_v = ex.out_k, ex.out_v
+    stats = serve.StepServer(ex, budget_bytes=1 << 30, direct=dx, direct_above=20000).run(reqs)
+    _check_results(reqs, ex, keys, vals)
+    assert sorted(closed) == sorted(opened)
+    names = list(opened.values())
+    assert sum(m.startswith("request ") for m in names) == len(reqs)
+    assert sum(m.startswith("step ") for m in names) == len(ex.phase_log)
+    assert sum(m.endswith(" single") for m in names) == sum(r.path == "single" for r in reqs)
+    assert stats.launches == len(ex.phase_log) + sum(r.path == "single" for r in reqs)
+
+
+def test_markers_call_the_roctx_library():
+    from paper_1105_6040_amd import markers
+    was = markers._enabled
+    markers.enable(True)
+    try:
+        if not markers.enabled():
+            pytest.skip("no roctx library on this machine")
+        rid = markers.start("test range")
+        markers.mark("test mark")
+        markers.stop(rid)
+    finally:
+        markers.enable(was)
