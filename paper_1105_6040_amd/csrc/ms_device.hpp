@@ -194,16 +194,19 @@ __device__ __forceinline__ void status_store(S* p, S v) {
 // ---------------------------------------------------------------------------
 // Tile ranking shared by the radix kernels.
 //
-// A tile of THREADS * KPT keys is held in registers, wave w owning tile
-// positions [w*64*KPT, (w+1)*64*KPT) and slot j of lane l holding position
-// w*64*KPT + j*64 + l.  `wave_rank` gives every key its rank among the keys of
-// the same digit in its wave, in position order (so equal digits keep their
-// order: the pass is stable), and leaves the wave's digit counts in `wh`
-// (kRadix counters of this wave, zeroed by the caller).
+// A tile of THREADS * R keys (R <= KPT rounds) is held in registers, wave w
+// owning tile positions [w*64*R, (w+1)*64*R) and slot j < R of lane l holding
+// position w*64*R + j*64 + l.  `wave_rank` gives every key its rank among the
+// keys of the same digit in its wave, in position order (so equal digits keep
+// their order: the pass is stable), and leaves the wave's digit counts in `wh`
+// (kRadix counters of this wave, zeroed by the caller).  Slots j >= R are not
+// read.  R is uniform across the block.
 template <typename K, int KPT>
-__device__ __forceinline__ void wave_rank(const K (&keys)[KPT], int shift, uint32_t (&rank)[KPT], uint32_t* wh) {
+__device__ __forceinline__ void wave_rank(const K (&keys)[KPT], int shift, uint32_t (&rank)[KPT], uint32_t* wh,
+                                          int rounds = KPT) {
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
+    if (j >= rounds) break;
     const uint32_t d = digit_of(keys[j], shift);
     const uint64_t peers = match_digit(d);
     const uint32_t old = wh[d];

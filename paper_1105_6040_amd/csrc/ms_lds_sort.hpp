@@ -7,6 +7,8 @@
 // key of the list are skipped.
 #pragma once
 
+#include <type_traits>
+
 #include "ms_device.hpp"
 
 namespace ms {
@@ -49,14 +51,20 @@ __device__ __forceinline__ void lds_sort_list(const K* __restrict__ kin, const u
   uint32_t* s_vals = sm.vals;
   uint32_t* s_diff = sm.diff;
 
-  const int first = wave * kWave * kKpt + static_cast<int>(lane);
+  // Only as many rounds of 64 keys per wave as the list needs: wave w holds
+  // list positions [w * 64 * R, (w + 1) * 64 * R), slot j < R of lane l
+  // position w * 64 * R + 64 * j + l; positions from len on hold padding that
+  // sorts after every key.
+  const int rounds = (len + kThreads - 1) / kThreads;  // R, 1 .. kKpt
+  const int first = wave * kWave * rounds + static_cast<int>(lane);
   K keys[kKpt];
   uint32_t vals[VALS ? kKpt : 1];
 #pragma unroll
   for (int j = 0; j < kKpt; ++j) {
     const int idx = first + j * kWave;
-    keys[j] = idx < len ? flip_key(kin[begin + idx], flip) : ~K(0);
-    if constexpr (VALS) vals[j] = idx < len ? vin[begin + idx] : 0u;
+    const bool real = j < rounds && idx < len;
+    keys[j] = real ? flip_key(kin[begin + idx], flip) : ~K(0);
+    if constexpr (VALS) vals[j] = real ? vin[begin + idx] : 0u;
   }
 
   // Which bits differ among the real keys?  Passes over constant digits are skipped.
@@ -66,45 +74,57 @@ __device__ __forceinline__ void lds_sort_list(const K* __restrict__ kin, const u
   K diff = 0;
 #pragma unroll
   for (int j = 0; j < kKpt; ++j)
-    if (first + j * kWave < len) diff |= keys[j] ^ k0;
+    if (j < rounds && first + j * kWave < len) diff |= keys[j] ^ k0;
   if (static_cast<uint32_t>(diff)) atomicOr(&s_diff[0], static_cast<uint32_t>(diff));
   if constexpr (sizeof(K) == 8)
     if (static_cast<uint32_t>(diff >> 32)) atomicOr(&s_diff[1], static_cast<uint32_t>(diff >> 32));
   __syncthreads();
   const uint64_t all_diff = (static_cast<uint64_t>(s_diff[1]) << 32) | s_diff[0];
 
-  for (int p = 0; p < static_cast<int>(sizeof(K)); ++p) {
-    const int shift = 8 * p;
-    if (((all_diff >> shift) & (kRadix - 1)) == 0) continue;  // uniform across the block
+  // Full lists run the rounds as compile-time loops; shorter ones stop at
+  // their last round.
+  auto digit_passes = [&](auto full) {
+    constexpr bool kFull = decltype(full)::value;
+    const int R = kFull ? kKpt : rounds;
+    for (int p = 0; p < static_cast<int>(sizeof(K)); ++p) {
+      const int shift = 8 * p;
+      if (((all_diff >> shift) & (kRadix - 1)) == 0) continue;  // uniform across the block
 
-    for (int i = tid; i < kWaves * kRadix; i += kThreads) (&s_whist[0][0])[i] = 0;
-    __syncthreads();
-    uint32_t rank[kKpt];
-    uint32_t* wh = s_whist[wave];
-    wave_rank(keys, shift, rank, wh);
-    __syncthreads();
-    uint32_t cnt;
-    tile_digit_starts<kThreads>(s_whist, sm.scan, &cnt);
-    __syncthreads();
+      for (int i = tid; i < kWaves * kRadix; i += kThreads) (&s_whist[0][0])[i] = 0;
+      __syncthreads();
+      uint32_t rank[kKpt];
+      uint32_t* wh = s_whist[wave];
+      wave_rank(keys, shift, rank, wh, R);
+      __syncthreads();
+      uint32_t cnt;
+      tile_digit_starts<kThreads>(s_whist, sm.scan, &cnt);
+      __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      const uint32_t pos = wh[digit_of(keys[j], shift)] + rank[j];
-      s_keys[pos] = keys[j];
-      if constexpr (VALS) s_vals[pos] = vals[j];
-    }
-    __syncthreads();
+      for (int j = 0; j < kKpt; ++j) {
+        if (j >= R) break;
+        const uint32_t pos = wh[digit_of(keys[j], shift)] + rank[j];
+        s_keys[pos] = keys[j];
+        if constexpr (VALS) s_vals[pos] = vals[j];
+      }
+      __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      keys[j] = s_keys[first + j * kWave];
-      if constexpr (VALS) vals[j] = s_vals[first + j * kWave];
+      for (int j = 0; j < kKpt; ++j) {
+        if (j >= R) break;
+        keys[j] = s_keys[first + j * kWave];
+        if constexpr (VALS) vals[j] = s_vals[first + j * kWave];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
+  };
+  if (rounds == kKpt)
+    digit_passes(std::true_type{});
+  else
+    digit_passes(std::false_type{});
 
 #pragma unroll
   for (int j = 0; j < kKpt; ++j) {
     const int idx = first + j * kWave;
-    if (idx < len) {
+    if (j < rounds && idx < len) {
       kout[begin + idx] = flip_key(keys[j], flip);
       if constexpr (VALS) vout[begin + idx] = vals[j];
     }

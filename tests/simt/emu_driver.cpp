@@ -365,6 +365,14 @@ int main(int argc, char** argv) {
     run_sort<uint64_t>(MS_KEY_U64, 10000, "few", true, false, 512);
     run_sort<uint32_t>(MS_KEY_I32, 100, "uniform", false, false, 256);
   }
+  if (what == "quick" || what == "lds") {
+    // one-workgroup in-LDS sorts: only the rounds of 64 keys per wave the
+    // list needs (one round, a partial last round, every round)
+    for (size_t n : {1, 2, 65, 511, 513, 1000, 4097, 8191})
+      run_sort<uint32_t>(n % 2 ? MS_KEY_I32 : MS_KEY_U32, n, n % 3 ? "uniform" : "few", n % 4 == 1, false, 512);
+    run_sort<uint64_t>(MS_KEY_U64, 2049, "few", true, false, 512);
+    run_sort<uint64_t>(MS_KEY_U64, 4096, "uniform", false, true, 512);
+  }
   if (what == "low12") {
     run_segmented<uint32_t>(MS_KEY_U32, {18599, 3000, 1200, 40000}, true, "low12");
     run_sort<uint32_t>(MS_KEY_U32, 18599, "low12", true, false, 1024);
