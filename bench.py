@@ -583,9 +583,10 @@ def segments_workload(dev, stream, seed=0, tune_it=True, hi=1_000_000):
     4.5e9 int32 keys; hi = 19,023: about 2^27, the total the batched
     configuration states), keys uniform in [0, 2^31) drawn on the device from
     a seeded generator, one sort_segmented call on each path that applies:
-    the work queue (one persistent launch for every phase), the segment
-    passes (a launch per phase) and the persistent kernel with one workgroup
-    per segment (segments averaging at most 8,192 keys take only the last)."""
+    the work queue (one persistent launch for every phase; segments
+    averaging more than 1,024 keys), the segment passes (a launch per phase;
+    more than 8,192) and the persistent kernel with one workgroup per
+    segment."""
     import torch
 
     from paper_1105_6040_amd import _native as N
@@ -600,14 +601,16 @@ def segments_workload(dev, stream, seed=0, tune_it=True, hi=1_000_000):
     k = torch.randint(0, 2**31, (n,), dtype=torch.int32, device=dev, generator=g)
     toff = torch.from_numpy(off).to(dev)
     out = torch.empty_like(k)
+    saved = N.tune_get(N.MS_TUNE_SEG_PASSES)
+    N.tune_set(N.MS_TUNE_SEG_PASSES, 2)  # sized for every path
     ws = torch.empty(N.workspace_size(N.MS_OP_SORT_SEGMENTED, N.MS_KEY_I32, False, n, lengths.size),
                      dtype=torch.uint8, device=dev)
+    N.tune_set(N.MS_TUNE_SEG_PASSES, saved)
     run = lambda: api.sort_segmented(k, toff, keys_out=out, ws=ws)  # noqa: E731
     paths = {}
-    saved = N.tune_get(N.MS_TUNE_SEG_PASSES)
-    modes = ((2, "work_queue_one_launch"), (1, "segment_passes"), (0, "persistent_one_wg_per_segment"))
-    if not tune.uses_segment_passes(n, int(lengths.size)):
-        modes = modes[2:]
+    nseg = int(lengths.size)
+    modes = [(m, name) for m, name in ((2, "work_queue_one_launch"), (1, "segment_passes"))
+             if tune.uses_segment_passes(n, nseg, m)] + [(0, "persistent_one_wg_per_segment")]
     for mode, name in modes:
         N.tune_set(N.MS_TUNE_SEG_PASSES, mode)
         _, per = time_steps(run, 3, 1, stream)

@@ -70,7 +70,9 @@ typedef enum ms_op {
  * n_total is the number of keys; num_segments the number of segments or runs
  * (ignored for the whole-list sorts); has_values selects the key/value form.
  * The figure depends only on the arguments, never on the data, so a serving
- * layer can admit work by exact bytes.  Returns MS_EINVAL for a NULL `bytes`,
+ * layer can admit work by exact bytes (and, for MS_OP_SORT_SEGMENTED, on
+ * whether MS_TUNE_SEG_PASSES is 2 at the time of the query: see
+ * ms_tune_set).  Returns MS_EINVAL for a NULL `bytes`,
  * MS_ENOTSUP for an unknown key type or op.
  */
 ms_status ms_workspace_size(ms_op op, ms_key_type kt, int has_values, uint64_t n_total,
@@ -116,9 +118,10 @@ ms_status part_offsets(uint64_t n, uint64_t num_parts, uint64_t *offsets_out, vo
  * vals_in / vals_out may both be NULL for a key-only sort.  In-place is
  * allowed under the same rule as sort_pairs.  Several segments averaging more
  * than 8,192 keys are sorted by whole-device digit passes over all of them
- * (unless MS_TUNE_SEG_PASSES is 0), other calls by three small planning
- * launches and one launch of a persistent kernel whose workgroups each take
- * whole segments; the result is the same.
+ * (unless MS_TUNE_SEG_PASSES is 0; with MS_TUNE_SEG_PASSES = 2 from 1,024 keys
+ * on average), other calls by three small planning launches and one launch
+ * of a persistent kernel whose workgroups each take whole segments; the
+ * result is the same.
  * The persistent kernel counts a segment's keys in 32 bits: on that path
  * every segment must hold fewer than 2^32 keys (a longer one is left in an
  * unspecified order, with no access outside it).  num_segments = 0 requires
@@ -278,7 +281,12 @@ const char *ms_last_error(void);
  *   MS_TUNE_SEG_PASSES    1 (the default): sort_segmented runs whole-device
  *                         digit passes when the segments average more than
  *                         8,192 keys, one launch per phase; 2: the same
- *                         phases as one persistent launch (a work queue of
+ *                         phases, for segments averaging more than 1,024
+ *                         keys (those averaging at most 8,192 only with a
+ *                         workspace sized while this value was 2, else they
+ *                         take the persistent kernel: their per-segment
+ *                         counters need up to 8 bytes per key), as one
+ *                         persistent launch (a work queue of
  *                         (phase, tile) items in 8 queues of consecutive
  *                         segments, one per XCD, a queue's items of phase f
  *                         starting once its phase f - 1 is done), after the

@@ -50,10 +50,14 @@ ms_status segmented_sort(const void* keys_in, const uint32_t* vals_in, void* key
                          uint32_t* vals_out, const uint64_t* offsets, uint64_t nseg, uint64_t n,
                          ms_key_type kt, void* ws, size_t ws_bytes, hipStream_t s);
 
-// Whole-device digit passes over segments that average more than 8,192
-// keys (radix.hip); sort_segmented takes this path when the host-known
-// counts allow it.
-bool segsweep_eligible(uint64_t n, uint64_t nseg);
+// Whole-device digit passes over many segments (radix.hip), in one of two
+// forms (MS_TUNE_SEG_PASSES = mode): a launch per phase (mode 1) for
+// segments averaging more than 8,192 keys, or the one-launch work queue
+// (mode 2) for segments averaging more than 1,024.  sort_segmented takes
+// this path when the host-known counts allow it for the mode; with
+// mode == 0 the threshold of the lowest form is returned (workspace sizing
+// covers every form).
+bool segsweep_eligible(uint64_t n, uint64_t nseg, int mode);
 size_t segsweep_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg);
 ms_status segsweep_sort(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
                         const uint64_t* offsets, uint64_t nseg, uint64_t n, ms_key_type kt, void* ws,

@@ -601,9 +601,13 @@ constexpr int kQOwners = kQStarts + kMaxQueues + 1;
 constexpr int kQWords = kQOwners + kMaxQueues;
 constexpr size_t kQWordsAll = 1024;
 static_assert(kQWords <= static_cast<int>(kQWordsAll), "queue table fits its block");
-// Used when the segments average more keys than one workgroup sorts in LDS
-// (8,192): shorter ones are sorted faster by one workgroup each.
+// A launch per phase is used when the segments average more keys than one
+// workgroup sorts in LDS (8,192): shorter ones are sorted faster by one
+// workgroup each.  The one-launch work queue sorts a one-tile segment whole
+// in LDS in its first phase, and pays off from segments averaging more than
+// 1,024 keys (below that a wave sorts each segment on its own).
 constexpr uint64_t kSegSweepMinAverage = 8192;
+constexpr uint64_t kSegQueueMinAverage = 1024;
 using SegSweepCfg = PassCfg<kSegSweepThreads>;  // the smallest tile: bounds the tile count
 
 // One tile of the segment passes.  `count` holds the tile's key count
@@ -1931,14 +1935,15 @@ ms_status radix_sort(const void* keys_in, const uint32_t* vals_in, void* keys_ou
   return fail(MS_ENOTSUP, "unknown key type %d", static_cast<int>(kt));
 }
 
-bool segsweep_eligible(uint64_t n, uint64_t nseg) {
+bool segsweep_eligible(uint64_t n, uint64_t nseg, int mode) {
   // Tile numbers and segment ids are 32-bit; the base kernel runs one block
   // per (segment, digit position) in one grid dimension.
   if (nseg < 1 || nseg * kMaxPasses >= (1ull << 31)) return false;
   const uint64_t tiles = (n + SegSweepCfg::kTile - 1) / SegSweepCfg::kTile + nseg;
-  // Segments averaging more than a tile (this also bounds the per-segment
-  // histograms and bases to 8 KiB per 8,192 keys).
-  return n > kSegSweepMinAverage * nseg && tiles < (1ull << 32);
+  // The average bounds the per-segment histograms and bases to 8 KiB per
+  // `min_average` keys.
+  const uint64_t min_average = mode == 1 ? kSegSweepMinAverage : kSegQueueMinAverage;
+  return n > min_average * nseg && tiles < (1ull << 32);
 }
 
 size_t segsweep_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg) {
@@ -1948,7 +1953,8 @@ size_t segsweep_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint6
 ms_status segsweep_sort(const void* keys_in, const uint32_t* vals_in, void* keys_out, uint32_t* vals_out,
                         const uint64_t* offsets, uint64_t nseg, uint64_t n, ms_key_type kt, void* ws,
                         size_t ws_bytes, hipStream_t s) {
-  if (!segsweep_eligible(n, nseg)) return fail(MS_EINVAL, "sort_segmented: internal: segment passes not eligible");
+  if (!segsweep_eligible(n, nseg, static_cast<int>(tune_get(MS_TUNE_SEG_PASSES))))
+    return fail(MS_EINVAL, "sort_segmented: internal: segment passes not eligible");
   const bool vals = vals_in != nullptr;
   const SegSweepLayout L = segsweep_layout(kt, vals, n, nseg);
   if (ws_bytes < L.total || !ws)

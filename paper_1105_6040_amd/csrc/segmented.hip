@@ -493,8 +493,14 @@ ms_status run_segmented(const void* kin, const uint32_t* vin, void* kout, uint32
 size_t segmented_workspace_bytes(ms_key_type kt, bool has_vals, uint64_t n, uint64_t nseg) {
   if (nseg == 1) return radix_workspace_bytes(kt, has_vals, n);
   const size_t persistent = seg_layout(kt, has_vals, n, nseg).total;
-  // Either path may run (MS_TUNE_SEG_PASSES), so the workspace covers both.
-  if (segsweep_eligible(n, nseg)) return std::max(persistent, segsweep_workspace_bytes(kt, has_vals, n, nseg));
+  // Either path may run (MS_TUNE_SEG_PASSES can change after sizing), so the
+  // workspace covers the segment passes whenever a launch per phase could
+  // take the call; segments averaging 1,024 - 8,192 keys are covered only
+  // when the one-launch queue is selected at sizing time (their per-segment
+  // counters cost up to 8 B per key).
+  const int mode = static_cast<int>(tune_get(MS_TUNE_SEG_PASSES));
+  if (segsweep_eligible(n, nseg, mode == 2 ? 2 : 1))
+    return std::max(persistent, segsweep_workspace_bytes(kt, has_vals, n, nseg));
   return persistent;
 }
 
@@ -504,11 +510,19 @@ ms_status segmented_sort(const void* keys_in, const uint32_t* vals_in, void* key
   // One segment is the whole list (offsets are {0, n} by contract): the
   // whole-list sort.
   if (nseg == 1) return radix_sort(keys_in, vals_in, keys_out, vals_out, n, kt, ws, ws_bytes, s);
-  // Long segments (more than 8,192 keys on average): whole-device digit
-  // passes over all of them (the host knows only the counts, which decide),
-  // unless the caller asked for the one-launch persistent kernel.
-  if (tune_get(MS_TUNE_SEG_PASSES) && segsweep_eligible(n, nseg))
-    return segsweep_sort(keys_in, vals_in, keys_out, vals_out, offsets, nseg, n, kt, ws, ws_bytes, s);
+  // Long segments: whole-device digit passes over all of them (a launch per
+  // phase from 8,192 keys on average, the one-launch work queue from 1,024;
+  // the host knows only the counts, which decide), unless the caller asked
+  // for the persistent kernel with one workgroup per segment.
+  const int seg_passes = static_cast<int>(tune_get(MS_TUNE_SEG_PASSES));
+  if (seg_passes && segsweep_eligible(n, nseg, seg_passes)) {
+    // Segments averaging 1,024 - 8,192 keys go to the queue only with a
+    // workspace sized for it; otherwise to the persistent kernel, which is
+    // their path by default.
+    const bool queue_only = !segsweep_eligible(n, nseg, 1);
+    if (!queue_only || ws_bytes >= segsweep_workspace_bytes(kt, vals_in != nullptr, n, nseg))
+      return segsweep_sort(keys_in, vals_in, keys_out, vals_out, offsets, nseg, n, kt, ws, ws_bytes, s);
+  }
   const bool vals = vals_in != nullptr;
   const SegLayout L = seg_layout(kt, vals, n, nseg);
   if (ws_bytes < L.total || !ws)

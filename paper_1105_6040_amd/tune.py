@@ -41,8 +41,11 @@ SEG_BLOCKS = (256, 512, 1024, 2048)
 SMALL_SORT = (64, 0)
 SEG_PASS_THREADS = (512, 1024)
 # sort_segmented runs whole-device digit passes when there are several
-# segments averaging more than this many keys (mi355sort.h).
+# segments averaging more than this many keys (mi355sort.h): a launch per
+# phase from SEG_PASS_MIN_AVERAGE, the one-launch work queue from
+# SEG_QUEUE_MIN_AVERAGE.
 SEG_PASS_MIN_AVERAGE = 8192
+SEG_QUEUE_MIN_AVERAGE = 1024
 SERVE_STEPS_INFLIGHT = (1, 2, 3)
 # Continuous-batching server: requests above this many pairs take a launch of
 # their own beside the steps (None: every request is batched), and how many of
@@ -61,10 +64,13 @@ def serving_candidates():
     return out
 
 
-def uses_segment_passes(n: int, nseg: int) -> bool:
+def uses_segment_passes(n: int, nseg: int, mode: int = 1) -> bool:
     """Whether sort_segmented of n keys in nseg segments takes the
-    whole-device segment passes (else the persistent kernel)."""
-    return nseg > 1 and n > SEG_PASS_MIN_AVERAGE * nseg
+    whole-device segment passes (else the persistent kernel) when
+    MS_TUNE_SEG_PASSES is `mode` (1: a launch per phase, 2: one launch)."""
+    if nseg <= 1 or mode == 0:
+        return False
+    return n > (SEG_PASS_MIN_AVERAGE if mode == 1 else SEG_QUEUE_MIN_AVERAGE) * nseg
 
 
 def size_class(n: int) -> int:
@@ -167,8 +173,14 @@ class Tuner:
         key = f"{self._device()}|segmented|kt{kt}|v{int(vals is not None)}|c{size_class(n)}|s{size_class(nseg)}"
         out = torch.empty_like(keys)
         vout = None if vals is None else torch.empty_like(vals)
-        ws = torch.empty(max(1, N.workspace_size(N.MS_OP_SORT_SEGMENTED, kt, vals is not None, n, nseg)),
-                         dtype=torch.uint8, device=keys.device)
+        # Sized with the one-launch queue selected: the largest of the forms.
+        saved = N.tune_get(N.MS_TUNE_SEG_PASSES)
+        N.tune_set(N.MS_TUNE_SEG_PASSES, 2)
+        try:
+            nbytes = N.workspace_size(N.MS_OP_SORT_SEGMENTED, kt, vals is not None, n, nseg)
+        finally:
+            N.tune_set(N.MS_TUNE_SEG_PASSES, saved)
+        ws = torch.empty(max(1, nbytes), dtype=torch.uint8, device=keys.device)
 
         def run():
             api.sort_segmented(keys, offsets, vals, out, vout, ws=ws)
@@ -176,9 +188,10 @@ class Tuner:
         # (segment passes on, pass threads, persistent workgroups, small-segment network)
         persistent = [(0, SEG_PASS_THREADS[0], b, m) for b, m in itertools.product(SEG_BLOCKS, SMALL_SORT)]
         space = persistent
-        if uses_segment_passes(n, nseg):
-            space = ([(2, SEG_PASS_THREADS[0], 0, SMALL_SORT[0])] +
-                     [(1, t, 0, SMALL_SORT[0]) for t in SEG_PASS_THREADS] + persistent)
+        if uses_segment_passes(n, nseg, 1):
+            space = [(1, t, 0, SMALL_SORT[0]) for t in SEG_PASS_THREADS] + space
+        if uses_segment_passes(n, nseg, 2):
+            space = [(2, SEG_PASS_THREADS[0], 0, SMALL_SORT[0])] + space
 
         def apply(p):
             N.tune_set(N.MS_TUNE_SEG_PASSES, p[0])
@@ -186,7 +199,7 @@ class Tuner:
             N.tune_set(N.MS_TUNE_SEG_BLOCKS, p[2])
             N.tune_set(N.MS_TUNE_SMALL_SORT, p[3])
 
-        return self._search(key + "|v3", space, apply, run, force)
+        return self._search(key + "|v4", space, apply, run, force)
 
     def tune_serving(self, run_server: Callable[[tuple], "object"], force: bool = False,
                      candidates: Optional[Iterable[tuple]] = None) -> dict:

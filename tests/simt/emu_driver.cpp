@@ -320,6 +320,9 @@ int main(int argc, char** argv) {
     run_segmented<uint64_t>(MS_KEY_U64, {3, 8192, 20000, 8191, 0, 1, 16384, 9000, 2, 30000}, false, "few");
     run_segmented<uint32_t>(MS_KEY_I32, {9000, 16383, 12000, 10000, 15000, 9500, 16000, 11000}, true, "uniform");
     run_segmented<uint32_t>(MS_KEY_U32, {18599, 3000, 1200, 40000}, true, "low12");
+    // segments averaging 1,024 - 8,192 keys: mostly one-tile segments sorted whole in phase 0
+    run_segmented<uint32_t>(MS_KEY_I32, {3000, 1, 0, 2500, 8192, 700, 8193, 4000, 1500, 2048}, false, "uniform");
+    run_segmented<uint64_t>(MS_KEY_U64, {2000, 3000, 0, 9000, 1200}, true, "few");
     run_malformed<uint32_t>(MS_KEY_I32, {0, 30000, 10000, 50000, 20000, 60000}, 60000, true, 2);
     run_malformed<uint32_t>(MS_KEY_U32, {0, 15000, 5000, 12000, 3000, 20000}, 20000, false, 2);
     ms_tune_set(MS_TUNE_SEG_PASSES, 1);

@@ -149,6 +149,33 @@ def test_tune_parameter_checks():
     assert get(6) == 0
 
 
+def test_segmented_workspace_for_the_queue_on_shorter_segments():
+    """Segments averaging 1,024 - 8,192 keys: the workspace grows for the
+    one-launch queue only while MS_TUNE_SEG_PASSES is 2 at sizing time (8 KiB
+    of counters and bases per segment), and stays at the persistent kernel's
+    otherwise."""
+    ws = N.workspace_size
+    old = N.tune_get(N.MS_TUNE_SEG_PASSES)
+    try:
+        for n, nseg in ((135_020_572, 50_000), (1 << 31, 1 << 18), (3000 * 7, 7)):
+            N.tune_set(N.MS_TUNE_SEG_PASSES, 1)
+            plain = ws(N.MS_OP_SORT_SEGMENTED, N.MS_KEY_I32, False, n, nseg)
+            N.tune_set(N.MS_TUNE_SEG_PASSES, 0)
+            assert ws(N.MS_OP_SORT_SEGMENTED, N.MS_KEY_I32, False, n, nseg) == plain
+            N.tune_set(N.MS_TUNE_SEG_PASSES, 2)
+            queue = ws(N.MS_OP_SORT_SEGMENTED, N.MS_KEY_I32, False, n, nseg)
+            assert 4 * n <= plain <= 1.3 * 4 * n + 16 * nseg + (1 << 20), (n, nseg, plain)
+            assert plain < queue <= plain + 8192 * nseg + 3 * 4 * n, (n, nseg, plain, queue)
+        # 1,024 keys on average or fewer: the persistent kernel in every mode
+        sizes = set()
+        for mode in (0, 1, 2):
+            N.tune_set(N.MS_TUNE_SEG_PASSES, mode)
+            sizes.add(ws(N.MS_OP_SORT_SEGMENTED, N.MS_KEY_I32, False, 1024 * 100, 100))
+        assert len(sizes) == 1
+    finally:
+        N.tune_set(N.MS_TUNE_SEG_PASSES, old)
+
+
 def test_segmented_workspace_stays_near_the_keys():
     """sort_segmented's workspace is the ping-pong copy of the keys plus a
     bounded overhead on either path (host arithmetic only): the segment

@@ -462,6 +462,47 @@ def test_sort_segmented_work_queue_random_mix(seed):
         N.tune_set(N.MS_TUNE_SEG_PASSES, old)
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_sort_segmented_work_queue_moderate_segments(seed):
+    """MS_TUNE_SEG_PASSES = 2 takes segments averaging more than 1,024 keys
+    (below one tile on average: most segments are sorted whole in LDS in the
+    queue's first phase, a few span tiles).  Every segment against the
+    oracle; with MS_TUNE_SEG_PASSES = 1 the same call (the persistent
+    kernel while the average is at most 8,192) gives the same bytes."""
+    rng = np.random.default_rng([12, seed])
+    nseg = int(rng.integers(3, 400))
+    lengths = rng.integers(1, 6000, nseg).astype(np.int64)
+    lengths[rng.integers(0, nseg, 3)] = rng.choice([0, 1, 8192, 8193, 20_000, 70_000], 3)
+    while lengths.sum() <= 1024 * nseg:
+        lengths[rng.integers(0, nseg)] += 5000
+    off = inputs.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    assert n > 1024 * nseg
+    dt = ("i32", "u32", "u64")[seed % 3]
+    say(f"work queue moderate seed={seed} {dt} nseg={nseg} n={n}")
+    k = inputs.keys(dt, n, ("uniform", "few")[seed % 2], seed=seed + 70)
+    v = np.arange(n, dtype=np.uint32) if seed % 2 else None
+    old = N.tune_get(N.MS_TUNE_SEG_PASSES)
+    try:
+        outs = []
+        for mode in (2, 1):
+            N.tune_set(N.MS_TUNE_SEG_PASSES, mode)
+            if v is None:
+                outs.append((host(api.sort_segmented(dev(k), dev(off))),))
+            else:
+                ko, vo = api.sort_segmented(dev(k), dev(off), dev(v))
+                outs.append((host(ko), host(vo)))
+    finally:
+        N.tune_set(N.MS_TUNE_SEG_PASSES, old)
+    if v is None:
+        assert np.array_equal(outs[0][0], oracle.sort_segmented(k, off))
+    else:
+        ek, ev = oracle.sort_segmented(k, off, v)
+        assert np.array_equal(outs[0][0], ek) and np.array_equal(outs[0][1], ev)
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("nseg,nlong", [(1025, 60), (2049, 130)])
 def test_sort_segmented_one_launch_for_long_segments(nseg, nlong):
     """With MS_TUNE_SEG_PASSES = 0 segments averaging > 8,192 keys take the
