@@ -253,6 +253,8 @@ def main():
     ap.add_argument("--segments", action="store_true",
                     help="instead of the headline: the 50,000-segment batched sort alone")
     ap.add_argument("--serving", action="store_true", help="instead of the headline: the serving stream alone")
+    ap.add_argument("--segments-hi", type=int, default=None,
+                    help="with --segments: only the workload with lengths log-uniform in [16, this]")
     ap.add_argument("--serving-requests", type=int, default=2000,
                     help="measured requests of the serving stream (after 200 warm-up ones)")
     args = ap.parse_args()
@@ -277,9 +279,11 @@ def main():
         print(json.dumps(process_sweep(dev, stream)), flush=True)
         return
     if args.segments:
-        print(json.dumps({"segments_50k": segments_workload(dev, stream, tune_it=not args.no_tune),
-                          "segments_50k_hi19023": segments_workload(dev, stream, tune_it=not args.no_tune,
-                                                                    hi=19_023)}), flush=True)
+        his = (1_000_000, 19_023) if args.segments_hi is None else (args.segments_hi,)
+        names = {1_000_000: "segments_50k", 19_023: "segments_50k_hi19023"}
+        print(json.dumps({names.get(hi, f"segments_50k_hi{hi}"): segments_workload(dev, stream, tune_it=not args.no_tune,
+                                                                                    hi=hi) for hi in his}),
+              flush=True)
         return
     if args.serving:
         print(json.dumps({"serving": serving_workload(dev, nreq=args.serving_requests,
