@@ -82,7 +82,7 @@ __global__ void agent_kernel(uint32_t* status, uint32_t* counter, const uint32_t
       excl = pred & St::kValMask;
       atomicAdd(reinterpret_cast<unsigned long long*>(hits), 1ull);
     } else {
-      excl = ms::lookback<uint32_t, uint32_t, 16>(st, tile, R);
+      excl = ms::lookback<uint32_t, uint32_t, 4>(st, tile, R);  // the passes' window
       atomicAdd(reinterpret_cast<unsigned long long*>(walks), 1ull);
     }
     ms::status_store(st, St::kInc | (excl + cnt));
@@ -142,6 +142,7 @@ static int run(int tiles) {
 int main() {
   int fails = 0;
   fails += run<1>(300);
+  fails += run<4>(400);
   fails += run<8>(500);
   fails += run<16>(700);
   fails += run_agent<256, 1, 16>(150);

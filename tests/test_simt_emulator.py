@@ -44,4 +44,4 @@ def test_lookback_under_concurrency(emu_dir):
                     "-o", exe, "-lpthread"], check=True)
     r = run(exe, workers=8)
     assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
-    assert r.stdout.count("ok   lookback") == 6
+    assert r.stdout.count("ok   lookback") == 7
