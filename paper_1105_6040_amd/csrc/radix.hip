@@ -82,7 +82,9 @@ struct PassCfg {
   // the status rows, so those tiles walk back by themselves.
   static constexpr bool kAgent = THREADS == 1024;
   static constexpr int kAgents = kAgent ? 4 : 0;
-  static constexpr int kAgentW = 8;
+  // Rows per chunk, measured on 2^28 int32 keys: 2 rows 1.16 ms per pass
+  // (the agents fall behind), 4 rows 0.813 ms, 8 rows 0.827, 16 rows 0.853.
+  static constexpr int kAgentW = 4;
 };
 constexpr int kMinPassTile = PassCfg<256>::kTile;  // workspace is sized for the smallest tile
 
