@@ -81,10 +81,12 @@ struct PassCfg {
   // rows.  Smaller tiles arrive faster than agents of their size can read
   // the status rows, so those tiles walk back by themselves.
   static constexpr bool kAgent = THREADS == 1024;
-  static constexpr int kAgents = kAgent ? 4 : 0;
-  // Rows per chunk, measured on 2^28 int32 keys: 2 rows 1.16 ms per pass
-  // (the agents fall behind), 4 rows 0.813 ms, 8 rows 0.827, 16 rows 0.853.
-  static constexpr int kAgentW = 4;
+  // Agents and rows per chunk, measured per pass on 2^28 int32 keys: 4
+  // agents of 2, 4, 8 or 16 rows 1.16 (the agents fall behind), 0.813,
+  // 0.827 and 0.853 ms; 2 agents of 4, 8 or 16 rows 1.02, 0.808 and 0.834
+  // ms; 1 agent of 16 rows 0.917 ms; 8 agents of 4 rows 0.839 ms.
+  static constexpr int kAgents = kAgent ? 2 : 0;
+  static constexpr int kAgentW = 8;
 };
 constexpr int kMinPassTile = PassCfg<256>::kTile;  // workspace is sized for the smallest tile
 

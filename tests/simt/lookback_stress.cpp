@@ -147,6 +147,6 @@ int main() {
   fails += run<16>(700);
   fails += run_agent<256, 1, 16>(150);
   fails += run_agent<512, 2, 16>(150);
-  fails += run_agent<1024, 4, 4>(150);  // the 1,024-thread pass's agents
+  fails += run_agent<1024, 2, 8>(150);  // the 1,024-thread pass's agents
   return fails ? 1 : 0;
 }
