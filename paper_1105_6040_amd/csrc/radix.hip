@@ -76,17 +76,19 @@ struct PassCfg {
   static constexpr int kThreads = THREADS;
   static constexpr int kKpt = 16;
   static constexpr int kTile = kThreads * kKpt;
-  // Look-back agents publish prefixes for 1,024-thread tiles: kAgents
-  // workgroups, each serving kRadix / kAgents digits with chunks of kAgentW
-  // rows.  Smaller tiles arrive faster than agents of their size can read
-  // the status rows, so those tiles walk back by themselves.
-  static constexpr bool kAgent = THREADS == 1024;
-  // Agents and rows per chunk, measured per pass on 2^28 int32 keys: 4
-  // agents of 2, 4, 8 or 16 rows 1.16 (the agents fall behind), 0.813,
-  // 0.827 and 0.853 ms; 2 agents of 4, 8 or 16 rows 1.02, 0.808 and 0.834
-  // ms; 1 agent of 16 rows 0.917 ms; 8 agents of 4 rows 0.839 ms.
+  // Look-back agents publish prefixes for tiles of 512 and 1,024 threads:
+  // kAgents workgroups, each serving kRadix / kAgents digits with chunks of
+  // kAgentW rows.  256-thread tiles arrive faster than agents of their size
+  // can read the status rows, so those tiles walk back by themselves.
+  static constexpr bool kAgent = THREADS >= 512;
+  // Agents and rows per chunk, measured per pass on 2^28 int32 keys
+  // (1,024 threads): 4 agents of 2, 4, 8 or 16 rows 1.16 (the agents fall
+  // behind), 0.813, 0.827 and 0.853 ms; 2 agents of 4, 8 or 16 rows 1.02,
+  // 0.808 and 0.834 ms; 1 agent of 16 rows 0.917 ms; 8 agents of 4 rows
+  // 0.839 ms.  2^26 (u64, u32) pairs (512 threads), whole sort: 2 agents of
+  // 8, 16 or 32 rows 4.39, 4.17 and 4.28 ms, none 4.31 ms.
   static constexpr int kAgents = kAgent ? 2 : 0;
-  static constexpr int kAgentW = 8;
+  static constexpr int kAgentW = THREADS == 1024 ? 8 : 16;
 };
 constexpr int kMinPassTile = PassCfg<256>::kTile;  // workspace is sized for the smallest tile
 
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(THREADS) void onesweep_kernel(
   // Keys of the tile after the current one, loaded straight into LDS: wave w
   // owns entries [w * 64 * KPT, (w + 1) * 64 * KPT), filled by its 4 x 16-byte
   // loads per lane (lane l's 16 bytes of load q at 16 * (q * 64 + l)).
-  constexpr bool kLdsPrefetch = PassCfg<THREADS>::kAgent && sizeof(K) == 4 && !VALS;
+  constexpr bool kLdsPrefetch = THREADS == 1024 && sizeof(K) == 4 && !VALS;
   __shared__ __attribute__((aligned(16))) uint32_t s_next[kLdsPrefetch ? kTile : 4];
   // Used by the look-back agent only.
   constexpr bool kAgent = PassCfg<THREADS>::kAgent;
@@ -1623,7 +1625,7 @@ template <typename K, bool VALS, int THREADS>
 constexpr int pass_lds_bytes() {
   constexpr int stage = padded16(PassCfg<THREADS>::kTile) * static_cast<int>(sizeof(K));
   constexpr int counts = SplitScratch<THREADS>::kCountWords * 4;
-  constexpr bool prefetch = PassCfg<THREADS>::kAgent && sizeof(K) == 4 && !VALS;
+  constexpr bool prefetch = THREADS == 1024 && sizeof(K) == 4 && !VALS;
   return (stage > counts ? stage : counts) + (VALS ? padded16(PassCfg<THREADS>::kTile) * 4 : 0) +
          (prefetch ? PassCfg<THREADS>::kTile * 4 : 0) + (PassCfg<THREADS>::kAgent ? THREADS * 8 : 0) + 4096;
 }
